@@ -1,0 +1,192 @@
+/*
+ * sca.h -- C ABI of libsca, the MI355X (gfx950) hot path of the fixed-stepsize
+ * successive-convex-approximation block method (AsyFLEXA, Algorithm 1 of Cannelli,
+ * Facchinei, Kungurtsev, Scutari, arXiv:1701.04900) for
+ *
+ *     min_x  1/2 ||A x - b||^2 - c ||x||^2 + lambda * sum_j h(x_j)
+ *     s.t.   -beta <= x_j <= beta,
+ *
+ * with h = |.| (LASSO, Section 4.2) or one of the DC regularisers of Section 4.3.
+ *
+ * One ROUND k (steps S.1-S.5 of Algorithm 1 for every drawn block, all reading the
+ * same x^k and r^k = A x^k - b):
+ *   S.1  block i is drawn iff word 0 of Philox4x32-10(counter = (i, k mod 2^32,
+ *        k div 2^32, instance), key = (seed mod 2^32, seed div 2^32)) is below
+ *        floor(select_p * 2^32)  (select_p = 1 draws every block);
+ *   S.2  for every coordinate j of a drawn block:
+ *          g_j  = a_j^T r - 2 c x_j - lambda * (h^-)'(x_j)
+ *          q_j  = ||a_j||^2 + tau
+ *          xh_j = clip(soft(x_j - g_j/q_j, lambda*eta/q_j), -beta, beta)
+ *        (the closed-form minimiser of the block surrogate, subproblem (2));
+ *   S.4  x_j += gamma_k (xh_j - x_j)   (update (3));
+ *        r += sum over moved j of a_j * dx_j  (keeps r = A x - b).
+ * gamma_k = gamma for a fixed step; with gamma_mu > 0 it follows
+ * gamma_{k+1} = gamma_k (1 - gamma_mu gamma_k) from gamma_0 = gamma (Section 4.1).
+ *
+ * Conventions for every entry point
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA tensors);
+ *     *_host are host pointers.  Scalars are passed by value.
+ *   - 'stream' is a hipStream_t (NULL = the null stream).  Work is enqueued on it in
+ *     order; entry points that return host scalars synchronise that stream and say so.
+ *   - Every argument is validated on the host before any launch; a failure returns
+ *     SCA_EINVAL (nothing is enqueued) and sca_last_error() describes it.
+ *   - dtype SCA_F32: A, b, x, r are float and every accumulation of the round is in
+ *     float; objective, merit, M_F and fresh residuals accumulate in double.
+ *     dtype SCA_F64: everything is double.
+ *   - Status codes are returned; no exception crosses the ABI.
+ */
+#ifndef SCA_H
+#define SCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCA_OK = 0,
+  SCA_EINVAL = 1,     /* invalid argument; nothing was enqueued                          */
+  SCA_ENOMEM = 2,     /* a device allocation failed                                      */
+  SCA_EHIP = 3,       /* a HIP runtime call failed                                       */
+  SCA_ENONFINITE = 4, /* the objective became NaN/Inf at a check (divergence)            */
+  SCA_ENOTCONV = 5    /* max_rounds reached before the tolerance (stats are filled in)   */
+} sca_status;
+
+typedef enum { SCA_F32 = 0, SCA_F64 = 1 } sca_dtype;
+
+/* Regulariser h (Section 4.3): L1 h=|x|; EXP h=1-exp(-theta|x|), eta=theta;
+ * LOG h=log(1+theta|x|)/log(1+theta), eta=theta/log(1+theta).  The concave part
+ * h^- = eta|x| - h is linearised in the best response. */
+typedef enum { SCA_REG_L1 = 0, SCA_REG_EXP = 1, SCA_REG_LOG = 2 } sca_reg;
+
+enum { SCA_FLAG_PROFILE = 1 }; /* time the kernels of sca_step with HIP events */
+
+typedef struct sca_problem sca_problem; /* opaque, owned by the library */
+
+typedef struct {
+  size_t struct_size;    /* = sizeof(sca_opts)                                           */
+  double gamma;          /* step (3), in (0, 1]; initial value of the diminishing rule     */
+  double gamma_mu;       /* >= 0; 0 = fixed step                                          */
+  double tau;            /* >= 0, proximal weight of the surrogate (q_j = ||a_j||^2 + tau) */
+  double select_p;       /* (0, 1], probability that a block is drawn in a round          */
+  uint64_t seed;         /* Philox key                                                    */
+  uint32_t instance;     /* Philox counter word 3                                         */
+  uint32_t flags;        /* SCA_FLAG_*                                                    */
+  int64_t max_rounds;    /* sca_solve: round budget                                       */
+  int64_t check_every;   /* sca_solve: rounds between objective checks (>= 1)             */
+  int64_t refresh_every; /* sca_solve: recompute r = Ax-b every this many checks (0 = no) */
+  double tol_rel_obj;    /* sca_solve: stop at (F - F_star)/|F_star| <= tol (0 = off)     */
+  double F_star;         /* reference optimum for tol_rel_obj                              */
+  double tol_merit;      /* sca_solve: stop at ||xh(x) - x||_inf <= tol (0 = off)          */
+} sca_opts;
+
+typedef struct {
+  size_t struct_size;    /* = sizeof(sca_stats)                                          */
+  int64_t rounds;        /* rounds run                                                    */
+  int64_t coord_updates; /* sum over rounds of the drawn coordinates                      */
+  double F;              /* final objective with a freshly computed residual (FP64 acc.)  */
+  double merit;          /* final ||xh(x) - x||_inf                                       */
+  double MF;             /* final ||M_F(x)||_2 (unit-step prox residual, Section 3)      */
+  double rel_err;        /* (F - F_star)/|F_star| when F_star != 0, else 0               */
+  double seconds;        /* host wall time of the call                                    */
+  int64_t nnz;           /* nonzeros of xh(x)                                             */
+  int32_t status;        /* sca_status of the solve                                       */
+  int32_t checks;        /* objective checks performed                                    */
+} sca_stats;
+
+/* Kernel kinds reported by sca_profile_get (indices into its arrays). */
+enum { SCA_K_SELECT = 0, SCA_K_GRAD = 1, SCA_K_COMPACT = 2, SCA_K_FOLD = 3, SCA_K_NKINDS = 4 };
+
+/* Library version string (static storage). */
+const char* sca_version(void);
+
+/* Message of the last failing call on this host thread (static, thread-local storage). */
+const char* sca_last_error(void);
+
+/* Create a problem over a dense A.
+ *  A_colmajor_dev: column j at A + j*lda, m valid rows; the buffer holds lda*n elements of
+ *    the dtype, base 16-byte aligned, lda >= m and lda a multiple of 16/sizeof(element).
+ *    Rows m..lda-1 are never read.  BORROWED: A must outlive the problem; it is not copied.
+ *  b_dev: m elements, borrowed.  lambda >= 0, c >= 0, beta > 0 (INFINITY = no box).
+ *  block_ptr_host: nblocks+1 ascending offsets, block_ptr[0] = 0, block_ptr[nblocks] = n,
+ *    every block nonempty (Assumption D4: a block is updated by one worker).  Copied.
+ * Computes ||a_j||^2 (FP64) and checks that b is finite; synchronises 'stream' once. */
+sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtype, int64_t m, int64_t n,
+                                    const void* A_colmajor_dev, int64_t lda, const void* b_dev,
+                                    double lambda, double c, double beta,
+                                    const int64_t* block_ptr_host, int64_t nblocks, void* stream);
+
+/* Create a problem over a sparse A given in CSR (row-major) form: rowptr_dev (m+1 int64),
+ * colidx_dev (nnz int32 in [0,n)), vals_dev (nnz of the dtype), b_dev (m).  The library
+ * builds and owns a column-major (CSC) copy with rows ascending inside each column; the
+ * caller may free the CSR once this call returns.  Other arguments as for the dense form.
+ * Synchronises 'stream'. */
+sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype, int64_t m, int64_t n,
+                                  int64_t nnz, const int64_t* rowptr_dev,
+                                  const int32_t* colidx_dev, const void* vals_dev,
+                                  const void* b_dev, double lambda, double c, double beta,
+                                  const int64_t* block_ptr_host, int64_t nblocks, void* stream);
+
+/* Select the regulariser (default SCA_REG_L1).  theta > 0 for EXP and LOG. */
+sca_status sca_problem_set_regularizer(sca_problem* p, sca_reg reg, double theta);
+
+/* Release the problem and its workspace (A and b stay with the caller).  NULL is a no-op. */
+void sca_problem_destroy(sca_problem* p);
+
+/* Run rounds round_begin .. round_begin+nrounds-1 in place on x_dev (n elements) and
+ * r_dev (m elements, 16-byte aligned), which must satisfy r = A x - b on entry (see
+ * sca_residual).  The step of round k is gamma_k from opts.  Stream-ordered; does not
+ * synchronise (except with SCA_FLAG_PROFILE, which waits for its events at the end). */
+sca_status sca_step(sca_problem* p, const sca_opts* opts, int64_t round_begin, int64_t nrounds,
+                    void* x_dev, void* r_dev, void* stream);
+
+/* r_dev <- A x_dev - b with FP64 accumulation, rounded to the dtype.  Stream-ordered. */
+sca_status sca_residual(sca_problem* p, const void* x_dev, void* r_dev, void* stream);
+
+/* Fill mask_dev[i] (uint8, nblocks) with 1 when block i is drawn in round k (step S.1).
+ * Stream-ordered.  Exposes the selection the rounds use. */
+sca_status sca_select_blocks(sca_problem* p, const sca_opts* opts, int64_t k, uint8_t* mask_dev,
+                             void* stream);
+
+/* Philox4x32-10 on the device: for i < count, in_dev[6i..6i+5] = (ctr0..3, key0..1),
+ * out_dev[4i..4i+3] = output words.  Stream-ordered. */
+sca_status sca_philox4x32_10(const uint32_t* in_dev, uint32_t* out_dev, int64_t count,
+                             void* stream);
+
+/* Stationarity report at x_dev with a fresh residual (FP64 accumulation):
+ * F, ||xh(x)-x||_inf, ||M_F(x)||_2 and nnz(xh(x)); any output pointer may be NULL.
+ * opts supplies tau.  Synchronises 'stream'. */
+sca_status sca_objective(sca_problem* p, const sca_opts* opts, const void* x_dev, double* F,
+                         double* merit, double* MF, int64_t* nnz, void* stream);
+
+/* Solve from x_dev (in: x^0, out: final x) until tol_rel_obj / tol_merit / max_rounds
+ * (Section 4.2 measures relative objective error, Section 4.3 the merit).  The stopping
+ * test runs every check_every rounds and is confirmed with a fresh residual.  stats may
+ * be NULL.  Synchronises 'stream'.  Returns SCA_ENOTCONV when the budget ran out. */
+sca_status sca_solve(sca_problem* p, const sca_opts* opts, void* x_dev, sca_stats* stats,
+                     void* stream);
+
+/* Implicit-differentiation adjoint at a fixed point x* = xh(x*) (regulariser L1 only).
+ * Support S = {j : xh_j(x*) != 0, |xh_j(x*)| < beta}, s = sign(xh_S); solves
+ * (A_S^T A_S - 2c I) w = xbar_S by conjugate gradients (FP64 dot products) to relative
+ * residual cg_tol (<= 0: 1e-12 in F64, 1e-6 in F32) within cg_maxit iterations, then
+ * bbar_dev = A_S w (m elements), *lambar_host = -s^T w.  opts supplies tau.
+ * Returns SCA_ENOTCONV when CG did not converge and SCA_EINVAL when H_S shows a
+ * non-positive curvature.  Synchronises 'stream'. */
+sca_status sca_adjoint(sca_problem* p, const sca_opts* opts, const void* xstar_dev,
+                       const void* xbar_dev, void* bbar_dev, double* lambar_host,
+                       double cg_tol, int64_t cg_maxit, void* stream);
+
+/* Accumulated kernel times (ms) and launch counts of sca_step calls made with
+ * SCA_FLAG_PROFILE, indexed by SCA_K_*; arrays of SCA_K_NKINDS entries.  reset != 0
+ * clears them after reading. */
+sca_status sca_profile_get(sca_problem* p, double* ms_host, int64_t* launches_host,
+                           double* bytes_host, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCA_H */

@@ -1,0 +1,642 @@
+// Host side of libsca: argument validation, problem objects, workspace, launch
+// sequences of the round, checks and the solve loop.  See include/sca.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sca.h"
+#include "sca_internal.h"
+#include "sca_kernels.h"
+
+using namespace sca;
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+sca_status sca::set_error(sca_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+extern "C" const char* sca_last_error(void) { return g_err; }
+extern "C" const char* sca_version(void) { return "libsca 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ helpers
+double sca::gamma_at_round(double g0, double mu, long long k) {
+  double g = g0;
+  for (long long i = 0; i < k; ++i) g = g * (1.0 - mu * g);
+  return g;
+}
+
+uint64_t sca::selection_threshold(double p) {
+  // floor(p * 2^32); p = 1 gives 2^32, i.e. every block.
+  return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+sca_status sca::validate_opts(const sca_opts* o) {
+  if (!o) return set_error(SCA_EINVAL, "opts is NULL");
+  if (o->struct_size != sizeof(sca_opts))
+    return set_error(SCA_EINVAL, "opts.struct_size %zu != %zu", o->struct_size, sizeof(sca_opts));
+  if (!(o->gamma > 0.0 && o->gamma <= 1.0))
+    return set_error(SCA_EINVAL, "gamma must lie in (0, 1]");
+  if (!(o->gamma_mu >= 0.0) || !std::isfinite(o->gamma_mu))
+    return set_error(SCA_EINVAL, "gamma_mu must be finite and >= 0");
+  if (!(o->tau >= 0.0) || !std::isfinite(o->tau))
+    return set_error(SCA_EINVAL, "tau must be finite and >= 0");
+  if (!(o->select_p > 0.0 && o->select_p <= 1.0))
+    return set_error(SCA_EINVAL, "select_p must lie in (0, 1]");
+  return SCA_OK;
+}
+
+static int device_cu_count() {
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu <= 0)
+    return 256;
+  return ncu;
+}
+
+sca_status sca::dev_alloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_error(SCA_ENOMEM, "hipMalloc(%zu) failed", bytes);
+  }
+  return SCA_OK;
+}
+
+BRParams sca::make_brparams(const sca_problem* p, double tau) {
+  BRParams bp;
+  bp.tau = tau;
+  bp.lam = p->lam;
+  bp.lam_eta = p->lam * p->eta;
+  bp.c2 = 2.0 * p->c;
+  bp.beta = p->beta;
+  bp.theta = p->theta;
+  bp.eta = p->eta;
+  bp.reg = p->reg;
+  return bp;
+}
+
+// ------------------------------------------------------------------ problem lifetime
+static sca_status common_checks(sca_dtype dtype, int64_t m, int64_t n, const void* b,
+                                double lambda, double c, double beta,
+                                const int64_t* block_ptr, int64_t nblocks) {
+  if (dtype != SCA_F32 && dtype != SCA_F64) return set_error(SCA_EINVAL, "unknown dtype");
+  if (m <= 0 || n <= 0 || m > INT32_MAX / 2 || n > INT32_MAX / 2)
+    return set_error(SCA_EINVAL, "m, n must lie in [1, 2^30)");
+  if (!b) return set_error(SCA_EINVAL, "b is NULL");
+  if (((uintptr_t)b) % (dtype == SCA_F32 ? 4 : 8))
+    return set_error(SCA_EINVAL, "b is not aligned to its element size");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda))
+    return set_error(SCA_EINVAL, "lambda must be finite and >= 0");
+  if (!(c >= 0.0) || !std::isfinite(c)) return set_error(SCA_EINVAL, "c must be finite and >= 0");
+  if (!(beta > 0.0)) return set_error(SCA_EINVAL, "beta must be > 0 (INFINITY for no box)");
+  if (!block_ptr || nblocks <= 0 || nblocks > n)
+    return set_error(SCA_EINVAL, "block_ptr must hold nblocks+1 offsets, 1 <= nblocks <= n");
+  if (block_ptr[0] != 0 || block_ptr[nblocks] != n)
+    return set_error(SCA_EINVAL, "block_ptr must start at 0 and end at n");
+  for (int64_t i = 0; i < nblocks; ++i)
+    if (block_ptr[i + 1] <= block_ptr[i])
+      return set_error(SCA_EINVAL, "block %lld is empty or block_ptr is not ascending",
+                       (long long)i);
+  if (c > 0.0 && !std::isfinite(beta))
+    return set_error(SCA_EINVAL, "c > 0 needs a finite box bound (else F is unbounded below)");
+  return SCA_OK;
+}
+
+static sca_status alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
+  const int n = (int)p->n;
+  const size_t es = p->esize;
+  const int nch = (n + kChunk - 1) / kChunk + 1;
+  sca_status st;
+#define ALLOC(ptr, bytes)                                       \
+  do {                                                          \
+    if ((st = dev_alloc((void**)&(ptr), (bytes))) != SCA_OK) return st; \
+  } while (0)
+  ALLOC(p->d_bp, sizeof(int) * (p->nblocks + 1));
+  ALLOC(p->d_cn2, sizeof(double) * n);
+  ALLOC(p->d_state, sizeof(RoundState));
+  ALLOC(p->d_sel_cols, sizeof(int) * n);
+  ALLOC(p->d_dx_sel, es * n);
+  ALLOC(p->d_chunk_cnt, sizeof(int) * nch);
+  ALLOC(p->d_J_idx, sizeof(int) * n);
+  ALLOC(p->d_J_val, es * n);
+  p->ldp = (p->m + 63) / 64 * 64;
+  ALLOC(p->d_part, sizeof(double) * kMaxGroups * p->ldp);
+  ALLOC(p->d_r64, sizeof(double) * p->ldp);
+  ALLOC(p->d_rtmp, es * p->ldp);
+  ALLOC(p->d_scal, sizeof(double) * 64);
+  ALLOC(p->d_int, sizeof(int) * 64);
+  p->obj_blocks = 256;
+  ALLOC(p->d_obj_part, sizeof(double) * 3 * p->obj_blocks);
+  p->probe_waves = 4 * 4 * p->ncu;
+  ALLOC(p->d_wmax, sizeof(double) * p->probe_waves);
+  ALLOC(p->d_wsum, sizeof(double) * p->probe_waves);
+  ALLOC(p->d_wcnt, sizeof(int) * p->probe_waves);
+#undef ALLOC
+  std::vector<int> bp32(p->nblocks + 1);
+  for (int64_t i = 0; i <= p->nblocks; ++i) bp32[i] = (int)block_ptr[i];
+  if (hipMemcpy(p->d_bp, bp32.data(), sizeof(int) * bp32.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return set_error(SCA_EHIP, "copy of block_ptr failed");
+  p->block_ptr_host.assign(block_ptr, block_ptr + p->nblocks + 1);
+  return SCA_OK;
+}
+
+static void free_workspace(sca_problem* p) {
+  void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state, p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
+                  p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
+                  p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
+                  p->csc_colptr, p->csc_rowidx, p->csc_vals, p->csr_tmp};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto& e : p->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  p->events.clear();
+}
+
+// Column norms, minimum column norm and a finite check of b; synchronises once.
+sca_status sca::finish_create(sca_problem* p, hipStream_t s) {
+  init_round_state(p, nullptr, 0, s);
+  if (p->sparse) {
+    launch_colnorm2_csc(p, s);
+  } else if (p->dtype == SCA_F32) {
+    hipLaunchKernelGGL(k_colnorm2<float>, dim3(4 * p->ncu), dim3(256), 0, s,
+                       (const float*)p->A, (long long)p->lda, (int)p->m, (int)p->n, p->d_cn2);
+  } else {
+    hipLaunchKernelGGL(k_colnorm2<double>, dim3(4 * p->ncu), dim3(256), 0, s,
+                       (const double*)p->A, (long long)p->lda, (int)p->m, (int)p->n, p->d_cn2);
+  }
+  if (hipMemsetAsync(p->d_int, 0, sizeof(int), s) != hipSuccess)
+    return set_error(SCA_EHIP, "memset failed");
+  if (p->dtype == SCA_F32)
+    hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(64), dim3(256), 0, s, (const float*)p->b,
+                       (long long)p->m, p->d_int);
+  else
+    hipLaunchKernelGGL(k_count_nonfinite<double>, dim3(64), dim3(256), 0, s, (const double*)p->b,
+                       (long long)p->m, p->d_int);
+  std::vector<double> cn2(p->n);
+  int bad = 0;
+  if (hipMemcpyAsync(cn2.data(), p->d_cn2, sizeof(double) * p->n, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(&bad, p->d_int, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SCA_EHIP, "set-up kernels failed: %s", hipGetErrorString(hipGetLastError()));
+  if (bad) return set_error(SCA_EINVAL, "b holds NaN or Inf");
+  double mn = INFINITY;
+  for (double v : cn2) {
+    if (!std::isfinite(v)) return set_error(SCA_EINVAL, "A holds NaN or Inf");
+    mn = std::min(mn, v);
+  }
+  p->cn2_min = mn;
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtype, int64_t m,
+                                               int64_t n, const void* A, int64_t lda,
+                                               const void* b, double lambda, double c,
+                                               double beta, const int64_t* block_ptr,
+                                               int64_t nblocks, void* stream) {
+  if (!out) return set_error(SCA_EINVAL, "out is NULL");
+  *out = nullptr;
+  sca_status st = common_checks(dtype, m, n, b, lambda, c, beta, block_ptr, nblocks);
+  if (st != SCA_OK) return st;
+  const size_t es = dtype == SCA_F32 ? 4 : 8;
+  if (!A) return set_error(SCA_EINVAL, "A is NULL");
+  if (((uintptr_t)A) % 16) return set_error(SCA_EINVAL, "A must be 16-byte aligned");
+  if (lda < m || (lda * (int64_t)es) % 16)
+    return set_error(SCA_EINVAL, "lda must be >= m and lda*sizeof(element) a multiple of 16");
+  sca_problem* p = new (std::nothrow) sca_problem();
+  if (!p) return set_error(SCA_ENOMEM, "host allocation failed");
+  p->dtype = dtype;
+  p->esize = es;
+  p->m = m;
+  p->n = n;
+  p->lda = lda;
+  p->A = A;
+  p->b = b;
+  p->lam = lambda;
+  p->c = c;
+  p->beta = beta;
+  p->nblocks = nblocks;
+  p->ncu = device_cu_count();
+  if ((st = alloc_workspace(p, block_ptr)) != SCA_OK ||
+      (st = finish_create(p, (hipStream_t)stream)) != SCA_OK) {
+    free_workspace(p);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_problem_set_regularizer(sca_problem* p, sca_reg reg, double theta) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  if (reg == SCA_REG_L1) {
+    p->reg = 0;
+    p->theta = 0.0;
+    p->eta = 1.0;
+    return SCA_OK;
+  }
+  if (reg != SCA_REG_EXP && reg != SCA_REG_LOG) return set_error(SCA_EINVAL, "unknown regulariser");
+  if (!(theta > 0.0) || !std::isfinite(theta)) return set_error(SCA_EINVAL, "theta must be > 0");
+  p->reg = (int)reg;
+  p->theta = theta;
+  p->eta = reg == SCA_REG_EXP ? theta : theta / std::log1p(theta);
+  return SCA_OK;
+}
+
+extern "C" void sca_problem_destroy(sca_problem* p) {
+  if (!p) return;
+  free_workspace(p);
+  delete p;
+}
+
+// ------------------------------------------------------------------ profiling
+void sca::prof_begin(sca_problem* p, hipStream_t s, int kind) {
+  if (!p->profiling) return;
+  if (p->ev_used >= p->events.size()) {
+    std::pair<hipEvent_t, hipEvent_t> e;
+    (void)hipEventCreate(&e.first);
+    (void)hipEventCreate(&e.second);
+    p->events.push_back(e);
+  }
+  p->ev_kind.resize(p->events.size());
+  p->ev_kind[p->ev_used] = kind;
+  (void)hipEventRecord(p->events[p->ev_used].first, s);
+}
+
+void sca::prof_end(sca_problem* p, hipStream_t s, double bytes) {
+  if (!p->profiling) return;
+  p->ev_bytes.resize(p->events.size());
+  p->ev_bytes[p->ev_used] = bytes;
+  (void)hipEventRecord(p->events[p->ev_used].second, s);
+  ++p->ev_used;
+}
+
+static void prof_collect(sca_problem* p) {
+  if (!p->profiling || p->ev_used == 0) return;
+  (void)hipEventSynchronize(p->events[p->ev_used - 1].second);
+  for (size_t i = 0; i < p->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->events[i].first, p->events[i].second) == hipSuccess) {
+      p->prof_ms[p->ev_kind[i]] += ms;
+      p->prof_n[p->ev_kind[i]] += 1;
+      p->prof_bytes[p->ev_kind[i]] += p->ev_bytes[i];
+    }
+  }
+  p->ev_used = 0;
+}
+
+extern "C" sca_status sca_profile_get(sca_problem* p, double* ms, int64_t* launches,
+                                      double* bytes, int reset) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  for (int k = 0; k < SCA_K_NKINDS; ++k) {
+    if (ms) ms[k] = p->prof_ms[k];
+    if (launches) launches[k] = p->prof_n[k];
+    if (bytes) bytes[k] = p->prof_bytes[k];
+    if (reset) {
+      p->prof_ms[k] = 0;
+      p->prof_n[k] = 0;
+      p->prof_bytes[k] = 0;
+    }
+  }
+  return SCA_OK;
+}
+
+// ------------------------------------------------------------------ launch sequences
+template <typename T>
+static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
+                               uint64_t Tthr, const BRParams& bp) {
+  const int m = (int)p->m, n = (int)p->n;
+  prof_begin(p, s, SCA_K_SELECT);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)p->nblocks, p->d_bp, o->seed,
+                     o->instance, Tthr, p->d_state, p->d_sel_cols);
+  prof_end(p, s, 0.0);
+  // Algorithmic bytes of the gradient pass: m*sizeof(T) per drawn coordinate (known on
+  // the host only in profiling mode, where it is computed from the expected count).
+  prof_begin(p, s, SCA_K_GRAD);
+  hipLaunchKernelGGL((k_grad_br<T, 8>), dim3(p->ncu * p->grad_wg_per_cu), dim3(256), 0, s,
+                     (const T*)p->A, (long long)p->lda, m, (const T*)r, x, p->d_cn2,
+                     p->d_sel_cols, p->d_state, (T*)p->d_dx_sel, bp);
+  prof_end(p, s, 0.0);
+  prof_begin(p, s, SCA_K_COMPACT);
+  const int nch = (n + kChunk - 1) / kChunk;
+  const int cgrid = std::max(1, std::min(nch, 2 * p->ncu));
+  int* S_ptr = (int*)((char*)p->d_state + offsetof(RoundState, S_cnt));
+  hipLaunchKernelGGL(k_compact_count<T>, dim3(cgrid), dim3(1024), 0, s, (const T*)p->d_dx_sel,
+                     (const int*)S_ptr, p->d_chunk_cnt);
+  hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s,
+                     (const T*)p->d_dx_sel, (const int*)p->d_sel_cols, (const int*)S_ptr,
+                     (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val, p->d_state);
+  prof_end(p, s, 0.0);
+  prof_begin(p, s, SCA_K_FOLD);
+  constexpr int VN = V16<T>::N;
+  const int nrt = (m + 256 * VN - 1) / (256 * VN);
+  const int fgrid = std::max(1, std::min(nrt * kMaxGroups, 8 * p->ncu));
+  hipLaunchKernelGGL((k_fold_partial<T, T>), dim3(fgrid), dim3(256), 0, s, (const T*)p->A,
+                     (long long)p->lda, m, (const int*)p->d_J_idx, (const T*)p->d_J_val,
+                     (const RoundState*)p->d_state, (T*)p->d_part, (long long)p->ldp);
+  hipLaunchKernelGGL((k_fold_reduce<T, T, T>), dim3((m + 255) / 256), dim3(256), 0, s,
+                     (const T*)r, 1.0, (const T*)p->d_part, (long long)p->ldp,
+                     (const RoundState*)p->d_state, m, r, (double*)nullptr);
+  prof_end(p, s, 0.0);
+}
+
+// Fresh residual with FP64 accumulation: r64 = A x - b (and r_out in the dtype if given).
+template <typename T>
+static void launch_residual_dense(sca_problem* p, const T* x, T* r_out, hipStream_t s) {
+  const int m = (int)p->m, n = (int)p->n;
+  int* N_ptr = (int*)((char*)p->d_state + offsetof(RoundState, n_all));
+  const int nch = (n + kChunk - 1) / kChunk;
+  const int cgrid = std::max(1, std::min(nch, 2 * p->ncu));
+  hipLaunchKernelGGL(k_compact_count<T>, dim3(cgrid), dim3(1024), 0, s, x, (const int*)N_ptr,
+                     p->d_chunk_cnt);
+  hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s, x, (const int*)nullptr,
+                     (const int*)N_ptr, (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val,
+                     p->d_state);
+  constexpr int VN = V16<T>::N;
+  const int nrt = (m + 256 * VN - 1) / (256 * VN);
+  const int fgrid = std::max(1, std::min(nrt * kMaxGroups, 8 * p->ncu));
+  hipLaunchKernelGGL((k_fold_partial<T, double>), dim3(fgrid), dim3(256), 0, s, (const T*)p->A,
+                     (long long)p->lda, m, (const int*)p->d_J_idx, (const T*)p->d_J_val,
+                     (const RoundState*)p->d_state, (double*)p->d_part, (long long)p->ldp);
+  hipLaunchKernelGGL((k_fold_reduce<T, double, T>), dim3((m + 255) / 256), dim3(256), 0, s,
+                     (const T*)p->b, -1.0, (const double*)p->d_part, (long long)p->ldp,
+                     (const RoundState*)p->d_state, m, r_out, p->d_r64);
+}
+
+template <typename T>
+static void launch_objective(sca_problem* p, const T* x, const void* r, bool r_is64,
+                             const BRParams& bp, double* out_dev, hipStream_t s) {
+  if (r_is64)
+    hipLaunchKernelGGL((k_obj_partial<T, double>), dim3(p->obj_blocks), dim3(256), 0, s,
+                       (const double*)r, (int)p->m, x, (int)p->n, bp, p->d_obj_part);
+  else
+    hipLaunchKernelGGL((k_obj_partial<T, T>), dim3(p->obj_blocks), dim3(256), 0, s,
+                       (const T*)r, (int)p->m, x, (int)p->n, bp, p->d_obj_part);
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, s, (const double*)p->d_obj_part,
+                     p->obj_blocks, p->c, p->lam, out_dev);
+}
+
+template <typename T>
+static void launch_probe(sca_problem* p, const T* x, const BRParams& bp, double* out_dev,
+                         hipStream_t s) {
+  if (p->sparse) {
+    launch_probe_csc(p, (const void*)x, bp, s);
+  } else {
+    hipLaunchKernelGGL((k_probe<T>), dim3(p->probe_waves / 4), dim3(256), 0, s, (const T*)p->A,
+                       (long long)p->lda, (int)p->m, (const double*)p->d_r64, x, (int)p->n,
+                       (const double*)p->d_cn2, bp, p->d_wmax, p->d_wsum, p->d_wcnt);
+  }
+  hipLaunchKernelGGL(k_probe_final, dim3(1), dim3(64), 0, s, (const double*)p->d_wmax,
+                     (const double*)p->d_wsum, (const int*)p->d_wcnt, p->probe_waves, out_dev);
+}
+
+// ------------------------------------------------------------------ dispatch helpers
+template <typename T>
+static void run_rounds_t(sca_problem* p, const sca_opts* o, int64_t nrounds, T* x, T* r,
+                         hipStream_t s) {
+  const uint64_t Tthr = selection_threshold(o->select_p);
+  const BRParams bp = make_brparams(p, o->tau);
+  for (int64_t i = 0; i < nrounds; ++i) {
+    if (p->sparse)
+      launch_round_csc(p, o, (void*)x, (void*)r, s, Tthr, bp);
+    else
+      launch_round_dense<T>(p, o, x, r, s, Tthr, bp);
+  }
+}
+
+void sca::residual_any(sca_problem* p, const void* x, void* r_out, hipStream_t s) {
+  if (p->sparse) {
+    launch_residual_csc(p, x, r_out, s);
+  } else if (p->dtype == SCA_F32) {
+    launch_residual_dense<float>(p, (const float*)x, (float*)r_out, s);
+  } else {
+    launch_residual_dense<double>(p, (const double*)x, (double*)r_out, s);
+  }
+}
+
+static void objective_any(sca_problem* p, const void* x, const void* r, bool r_is64,
+                          const BRParams& bp, double* out_dev, hipStream_t s) {
+  if (p->dtype == SCA_F32)
+    launch_objective<float>(p, (const float*)x, r, r_is64, bp, out_dev, s);
+  else
+    launch_objective<double>(p, (const double*)x, r, r_is64, bp, out_dev, s);
+}
+
+static void probe_any(sca_problem* p, const void* x, const BRParams& bp, double* out_dev,
+                      hipStream_t s) {
+  if (p->dtype == SCA_F32)
+    launch_probe<float>(p, (const float*)x, bp, out_dev, s);
+  else
+    launch_probe<double>(p, (const double*)x, bp, out_dev, s);
+}
+
+static sca_status check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(SCA_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return SCA_OK;
+}
+
+static sca_status check_tau(const sca_problem* p, double tau) {
+  if (!(p->cn2_min + tau > 0.0))
+    return set_error(SCA_EINVAL, "a column of A is zero and tau = 0: q_j = 0");
+  return SCA_OK;
+}
+
+// Round counter and step of round_begin; clears the coordinate-update counter.
+void sca::init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begin, hipStream_t s) {
+  const double g = o ? gamma_at_round(o->gamma, o->gamma_mu, round_begin) : 1.0;
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, p->d_state, (long long)round_begin,
+                     g, o ? o->gamma_mu : 0.0, (int)p->n, 1);
+}
+
+// ------------------------------------------------------------------ public entry points
+extern "C" sca_status sca_step(sca_problem* p, const sca_opts* o, int64_t round_begin,
+                               int64_t nrounds, void* x, void* r, void* stream) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  sca_status st = validate_opts(o);
+  if (st != SCA_OK) return st;
+  if ((st = check_tau(p, o->tau)) != SCA_OK) return st;
+  if (round_begin < 0 || nrounds < 0) return set_error(SCA_EINVAL, "negative round range");
+  if (!x || !r) return set_error(SCA_EINVAL, "x or r is NULL");
+  if (((uintptr_t)r) % 16) return set_error(SCA_EINVAL, "r must be 16-byte aligned");
+  if (((uintptr_t)x) % p->esize) return set_error(SCA_EINVAL, "x is misaligned");
+  hipStream_t s = (hipStream_t)stream;
+  p->profiling = (o->flags & SCA_FLAG_PROFILE) != 0;
+  init_round_state(p, o, round_begin, s);
+  if (p->dtype == SCA_F32)
+    run_rounds_t<float>(p, o, nrounds, (float*)x, (float*)r, s);
+  else
+    run_rounds_t<double>(p, o, nrounds, (double*)x, (double*)r, s);
+  st = check_launch("sca_step");
+  prof_collect(p);
+  p->profiling = false;
+  return st;
+}
+
+extern "C" sca_status sca_residual(sca_problem* p, const void* x, void* r, void* stream) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  if (!x || !r) return set_error(SCA_EINVAL, "x or r is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  residual_any(p, x, r, s);
+  return check_launch("sca_residual");
+}
+
+extern "C" sca_status sca_select_blocks(sca_problem* p, const sca_opts* o, int64_t k,
+                                        uint8_t* mask, void* stream) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  sca_status st = validate_opts(o);
+  if (st != SCA_OK) return st;
+  if (!mask || k < 0) return set_error(SCA_EINVAL, "mask is NULL or k < 0");
+  hipLaunchKernelGGL(k_select_mask, dim3(std::max<int64_t>(1, std::min<int64_t>(
+                                        1024, (p->nblocks + 255) / 256))),
+                     dim3(256), 0, (hipStream_t)stream, (int)p->nblocks, o->seed, o->instance,
+                     selection_threshold(o->select_p), (long long)k, mask);
+  return check_launch("sca_select_blocks");
+}
+
+extern "C" sca_status sca_philox4x32_10(const uint32_t* in, uint32_t* out, int64_t count,
+                                        void* stream) {
+  if (count < 0 || (count > 0 && (!in || !out)))
+    return set_error(SCA_EINVAL, "bad philox arguments");
+  if (count == 0) return SCA_OK;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)std::min<int64_t>(1024, (count + 255) / 256)),
+                     dim3(256), 0, (hipStream_t)stream, in, out, (long long)count);
+  return check_launch("sca_philox4x32_10");
+}
+
+// F (fresh residual), merit, M_F, nnz into host scalars.  Synchronises.
+sca_status sca::report(sca_problem* p, const sca_opts* o, const void* x, double* F,
+                       double* merit, double* MF, int64_t* nnz, hipStream_t s) {
+  const BRParams bp = make_brparams(p, o->tau);
+  residual_any(p, x, nullptr, s);
+  objective_any(p, x, p->d_r64, true, bp, p->d_scal, s);
+  const bool want_probe = merit || MF || nnz;
+  if (want_probe) probe_any(p, x, bp, p->d_scal + 8, s);
+  double h[16];
+  if (hipMemcpyAsync(h, p->d_scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SCA_EHIP, "objective: %s", hipGetErrorString(hipGetLastError()));
+  if (F) *F = h[0];
+  if (merit) *merit = h[8];
+  if (MF) *MF = h[9];
+  if (nnz) *nnz = (int64_t)h[10];
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_objective(sca_problem* p, const sca_opts* o, const void* x, double* F,
+                                    double* merit, double* MF, int64_t* nnz, void* stream) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  sca_status st = validate_opts(o);
+  if (st != SCA_OK) return st;
+  if ((st = check_tau(p, o->tau)) != SCA_OK) return st;
+  if (!x) return set_error(SCA_EINVAL, "x is NULL");
+  return report(p, o, x, F, merit, MF, nnz, (hipStream_t)stream);
+}
+
+extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_stats* stats,
+                                void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  sca_status st = validate_opts(o);
+  if (st != SCA_OK) return st;
+  if ((st = check_tau(p, o->tau)) != SCA_OK) return st;
+  if (!x) return set_error(SCA_EINVAL, "x is NULL");
+  if (stats && stats->struct_size != sizeof(sca_stats))
+    return set_error(SCA_EINVAL, "stats.struct_size mismatch");
+  if (o->max_rounds < 0 || o->check_every < 1 || o->refresh_every < 0)
+    return set_error(SCA_EINVAL, "max_rounds >= 0, check_every >= 1, refresh_every >= 0");
+  if (o->tol_rel_obj > 0.0 && !(std::isfinite(o->F_star) && o->F_star != 0.0))
+    return set_error(SCA_EINVAL, "tol_rel_obj needs a finite nonzero F_star");
+  hipStream_t s = (hipStream_t)stream;
+  const BRParams bp = make_brparams(p, o->tau);
+  void* r = p->d_rtmp;  // running residual in the dtype (library-owned)
+  // r^0 = A x^0 - b (FP64 accumulation); round counter and step from round 0
+  init_round_state(p, o, 0, s);
+  residual_any(p, x, r, s);
+  int64_t k = 0;
+  int32_t checks = 0;
+  sca_status result = SCA_ENOTCONV;
+  double F = NAN;
+  while (k < o->max_rounds) {
+    const int64_t nr = std::min<int64_t>(o->check_every, o->max_rounds - k);
+    if (p->dtype == SCA_F32)
+      run_rounds_t<float>(p, o, nr, (float*)x, (float*)r, s);
+    else
+      run_rounds_t<double>(p, o, nr, (double*)x, (double*)r, s);
+    k += nr;
+    ++checks;
+    if (o->refresh_every > 0 && checks % o->refresh_every == 0) residual_any(p, x, r, s);
+    objective_any(p, x, r, false, bp, p->d_scal, s);
+    if (hipMemcpyAsync(&F, p->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return set_error(SCA_EHIP, "solve: %s", hipGetErrorString(hipGetLastError()));
+    if (!std::isfinite(F)) {
+      result = SCA_ENONFINITE;
+      break;
+    }
+    bool done = false;
+    if (o->tol_rel_obj > 0.0 && (F - o->F_star) / std::fabs(o->F_star) <= o->tol_rel_obj) {
+      double Ff;  // confirm with a fresh residual
+      if ((st = report(p, o, x, &Ff, nullptr, nullptr, nullptr, s)) != SCA_OK) return st;
+      done = (Ff - o->F_star) / std::fabs(o->F_star) <= o->tol_rel_obj;
+      if (!done) residual_any(p, x, r, s);  // the running residual drifted: restart it
+    }
+    if (!done && o->tol_merit > 0.0) {
+      double mer;
+      if ((st = report(p, o, x, nullptr, &mer, nullptr, nullptr, s)) != SCA_OK) return st;
+      done = mer <= o->tol_merit;
+    }
+    if (done) {
+      result = SCA_OK;
+      break;
+    }
+  }
+  if (o->max_rounds == 0 || (o->tol_rel_obj <= 0.0 && o->tol_merit <= 0.0 && result == SCA_ENOTCONV))
+    result = SCA_OK;  // no tolerance asked: running the budget is success
+  double Ff = NAN, mer = NAN, mf = NAN;
+  int64_t nnz = 0;
+  if (result != SCA_ENONFINITE) {
+    if ((st = report(p, o, x, &Ff, &mer, &mf, &nnz, s)) != SCA_OK) return st;
+  }
+  int64_t updates = 0;
+  if (hipMemcpyAsync(&updates, (char*)p->d_state + offsetof(RoundState, coord_updates),
+                     sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SCA_EHIP, "solve: %s", hipGetErrorString(hipGetLastError()));
+  if (stats) {
+    stats->rounds = k;
+    stats->coord_updates = updates;
+    stats->F = Ff;
+    stats->merit = mer;
+    stats->MF = mf;
+    stats->rel_err = (o->F_star != 0.0 && std::isfinite(o->F_star))
+                         ? (Ff - o->F_star) / std::fabs(o->F_star)
+                         : 0.0;
+    stats->nnz = nnz;
+    stats->status = result;
+    stats->checks = checks;
+    stats->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (result == SCA_ENONFINITE) return set_error(SCA_ENONFINITE, "objective became non-finite");
+  if (result == SCA_ENOTCONV) return set_error(SCA_ENOTCONV, "max_rounds reached");
+  return SCA_OK;
+}

@@ -1,0 +1,492 @@
+// gfx950 kernels of one SCA round over a dense column-major A, plus the FP64
+// reductions used for checks.  All kernels are deterministic: no floating-point
+// atomics, every sum has a fixed order; integer atomics only hand out work.
+#pragma once
+#include "sca_device.h"
+
+namespace sca {
+
+// Per-problem device state, updated by the kernels of a round.
+struct RoundState {
+  long long k;              // index of the next round to run
+  long long coord_updates;  // sum of drawn coordinates over the rounds run
+  double gamma_cur;         // step of the round in flight
+  double gamma_next;        // step of the following round
+  double gamma_mu;          // diminishing-rule parameter (0 = fixed step)
+  int S_cnt;                // coordinates drawn in the round in flight
+  int work_ctr;             // next work item of the gradient kernel
+  int J_cnt;                // entries of the compacted list (moved coordinates)
+  int G;                    // fold: list entries per column group
+  int ngroups;              // fold: number of column groups
+  int n_all;                // n (length of a compaction over every coordinate)
+};
+
+// Scalars of the best response (subproblem (2) in closed form).
+struct BRParams {
+  double tau;      // proximal weight
+  double lam;      // lambda
+  double lam_eta;  // lambda * eta: soft-threshold level before division by q
+  double c2;       // 2c
+  double beta;     // box bound (inf = none)
+  double theta;    // regulariser shape
+  double eta;      // slope of h at 0
+  int reg;         // 0 l1, 1 exp, 2 log
+};
+
+constexpr int kChunk = 1024;   // compaction chunk (one 1024-thread workgroup)
+constexpr int kMaxGroups = 128; // fold: upper bound on column groups per call
+
+// Derivative of h^- = eta|x| - h (the linearised concave part of the DC regularisers).
+template <typename T> __device__ __forceinline__ T dh_minus(T x, const BRParams& p) {
+  const T ax = fabs(x);
+  T d;
+  if (p.reg == 1) {
+    d = (T)p.theta * ((T)1 - exp(-(T)p.theta * ax));
+  } else {
+    d = (T)p.eta * ((T)p.theta * ax) / ((T)1 + (T)p.theta * ax);
+  }
+  return x > (T)0 ? d : (x < (T)0 ? -d : (T)0);
+}
+
+template <typename T> __device__ __forceinline__ T h_value(T x, const BRParams& p) {
+  const T ax = fabs(x);
+  if (p.reg == 0) return ax;
+  if (p.reg == 1) return (T)1 - exp(-(T)p.theta * ax);
+  return log1p((T)p.theta * ax) / (T)log1p(p.theta);
+}
+
+// clip(soft(v, thr), -beta, beta)
+template <typename T> __device__ __forceinline__ T soft_clip(T v, T thr, T beta) {
+  const T av = fabs(v) - thr;
+  T t = av > (T)0 ? copysign(av, v) : (T)0;
+  return fmin(fmax(t, -beta), beta);
+}
+
+// Dot product of one column (m rows, 16-byte aligned) with r, by one wave64; every lane
+// returns the sum.  U independent 16-byte loads per lane are kept in flight.
+template <typename TA, typename TR, typename Acc, int U>
+__device__ __forceinline__ Acc col_dot(const TA* __restrict__ col, const TR* __restrict__ r,
+                                       int m, int lane) {
+  typedef typename V16<TA>::v VA;
+  constexpr int VN = V16<TA>::N;
+  const int nvec = m / VN;
+  const VA* __restrict__ cv = reinterpret_cast<const VA*>(col);
+  Acc acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = (Acc)0;
+  int i = lane;
+  for (; i + 64 * (U - 1) < nvec; i += 64 * U) {
+    VA a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = __builtin_nontemporal_load(cv + i + 64 * u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int base = (i + 64 * u) * VN;
+      if constexpr (sizeof(TR) == sizeof(TA)) {
+        const VA rv = *reinterpret_cast<const VA*>(r + base);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[u] += (Acc)a[u][e] * (Acc)rv[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[u] += (Acc)a[u][e] * (Acc)r[base + e];
+      }
+    }
+  }
+  for (; i < nvec; i += 64) {
+    const VA a = __builtin_nontemporal_load(cv + i);
+#pragma unroll
+    for (int e = 0; e < VN; ++e) acc[0] += (Acc)a[e] * (Acc)r[i * VN + e];
+  }
+  Acc s = acc[0];
+#pragma unroll
+  for (int u = 1; u < U; ++u) s += acc[u];
+  const int tr = nvec * VN + lane;
+  if (tr < m) s += (Acc)col[tr] * (Acc)r[tr];
+  return wave_sum(s);
+}
+
+// ------------------------------------------------------------------ set-up kernels
+template <typename T>
+__global__ void __launch_bounds__(256) k_colnorm2(const T* __restrict__ A, long long lda, int m,
+                                                  int n, double* __restrict__ cn2) {
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * 4;
+  for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < n; j += nw) {
+    const T* col = A + (size_t)j * lda;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double v = (double)col[i];
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) cn2[j] = s;
+  }
+}
+
+template <typename T>
+static __global__ void k_count_nonfinite(const T* __restrict__ v, long long len, int* __restrict__ bad) {
+  int local = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x)
+    local |= !isfinite((double)v[i]);
+  if (local) atomicOr(bad, 1);
+}
+
+static __global__ void k_init_state(RoundState* st, long long k, double gamma, double mu, int n_all,
+                             int reset_updates) {
+  st->k = k;
+  if (reset_updates) st->coord_updates = 0;
+  st->gamma_cur = gamma;
+  st->gamma_next = gamma;
+  st->gamma_mu = mu;
+  st->S_cnt = 0;
+  st->work_ctr = 0;
+  st->J_cnt = 0;
+  st->G = 1;
+  st->ngroups = 0;
+  st->n_all = n_all;
+}
+
+// ------------------------------------------------------------------ S.1: block draw
+// One 1024-thread workgroup: each thread owns a contiguous range of blocks, the drawn
+// coordinates are listed in ascending order.  Also advances the round counter and the
+// step of the diminishing rule, and resets the gradient work counter.
+static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* __restrict__ bp,
+                                                 uint64_t seed, uint32_t inst, uint64_t T,
+                                                 RoundState* __restrict__ st,
+                                                 int* __restrict__ sel_cols) {
+  __shared__ int sh[17];
+  const long long k = st->k;
+  const int per = (nblocks + 1023) / 1024;
+  const int b0 = min(nblocks, (int)threadIdx.x * per);
+  const int b1 = min(nblocks, b0 + per);
+  int cnt = 0;
+  for (int i = b0; i < b1; ++i)
+    if (block_drawn((uint32_t)i, (uint64_t)k, inst, seed, T)) cnt += bp[i + 1] - bp[i];
+  int total;
+  int off = block_exclusive_scan_1024(cnt, sh, &total);
+  for (int i = b0; i < b1; ++i) {
+    if (block_drawn((uint32_t)i, (uint64_t)k, inst, seed, T)) {
+      for (int c = bp[i]; c < bp[i + 1]; ++c) sel_cols[off++] = c;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->S_cnt = total;
+    st->work_ctr = 0;
+    st->coord_updates += total;
+    st->k = k + 1;
+    const double g = st->gamma_next;
+    st->gamma_cur = g;
+    st->gamma_next = g * (1.0 - st->gamma_mu * g);
+  }
+}
+
+static __global__ void k_select_mask(int nblocks, uint64_t seed, uint32_t inst, uint64_t T, long long k,
+                              uint8_t* __restrict__ mask) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nblocks; i += gridDim.x * blockDim.x)
+    mask[i] = block_drawn((uint32_t)i, (uint64_t)k, inst, seed, T) ? 1 : 0;
+}
+
+static __global__ void k_philox(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                         long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {in[6 * i], in[6 * i + 1], in[6 * i + 2], in[6 * i + 3]};
+    philox4x32_10(c, in[6 * i + 4], in[6 * i + 5]);
+    for (int w = 0; w < 4; ++w) out[4 * i + w] = c[w];
+  }
+}
+
+// ------------------------------------------------------------------ S.2 + S.4
+// One wave per drawn coordinate j (work handed out by an integer counter, next item
+// prefetched): g_j = a_j^T r streamed from HBM, then the closed-form best response and
+// the relaxed step.  dx_sel[t] receives the move of the t-th drawn coordinate.
+template <typename T, int U>
+__global__ void __launch_bounds__(256)
+k_grad_br(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
+          T* __restrict__ x, const double* __restrict__ cn2, const int* __restrict__ sel_cols,
+          RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp) {
+  const int lane = threadIdx.x & 63;
+  const int S = st->S_cnt;
+  const T gamma = (T)st->gamma_cur;
+  int t = 0;
+  if (lane == 0) t = atomicAdd(&st->work_ctr, 1);
+  t = __shfl(t, 0, 64);
+  while (t < S) {
+    int tn = 0;
+    if (lane == 0) tn = atomicAdd(&st->work_ctr, 1);
+    const int j = sel_cols[t];
+    const T dot = col_dot<T, T, T, U>(A + (size_t)j * lda, r, m, lane);
+    if (lane == 0) {
+      const T xj = x[j];
+      T g = dot - (T)bp.c2 * xj;
+      if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+      const T q = (T)(cn2[j] + bp.tau);
+      const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
+      const T d = gamma * (xh - xj);
+      x[j] = xj + d;
+      dx_sel[t] = d;
+    }
+    t = __shfl(tn, 0, 64);
+  }
+}
+
+// ------------------------------------------------------------------ compaction
+// Two passes over v[0..N): per-chunk nonzero counts, then an ordered scatter of
+// (index, value) for the nonzero entries.  N is read from device memory.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_compact_count(const T* __restrict__ v,
+                                                        const int* __restrict__ N_ptr,
+                                                        int* __restrict__ chunk_cnt) {
+  __shared__ int sh[16];
+  const int N = *N_ptr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = blockIdx.x; c * kChunk < N; c += gridDim.x) {
+    const int t = c * kChunk + threadIdx.x;
+    const bool nz = t < N && v[t] != (T)0;
+    const uint64_t bal = __ballot(nz);
+    if (lane == 0) sh[wave] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int s = 0;
+      for (int w = 0; w < 16; ++w) s += sh[w];
+      chunk_cnt[c] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Writes list entries in ascending position; the workgroup that owns the last chunk
+// stores the count and the fold's column grouping (G entries per group, <= kMaxGroups).
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_compact_scatter(const T* __restrict__ v, const int* __restrict__ idx,
+                  const int* __restrict__ N_ptr, const int* __restrict__ chunk_cnt,
+                  int* __restrict__ J_idx, T* __restrict__ J_val, RoundState* __restrict__ st) {
+  __shared__ int sh[17];
+  __shared__ int sh_base;
+  const int N = *N_ptr;
+  const int nch = (N + kChunk - 1) / kChunk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (N == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    st->J_cnt = 0;
+    st->G = 1;
+    st->ngroups = 0;
+  }
+  for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+    // base = sum of the counts of the chunks before c (fixed order)
+    int part = 0;
+    for (int q = threadIdx.x; q < c; q += 1024) part += chunk_cnt[q];
+    int tot;
+    (void)block_exclusive_scan_1024(part, sh, &tot);
+    if (threadIdx.x == 0) sh_base = tot;
+    __syncthreads();
+    const int base = sh_base;
+    const int t = c * kChunk + threadIdx.x;
+    const bool nz = t < N && v[t] != (T)0;
+    const uint64_t bal = __ballot(nz);
+    if (lane == 0) sh[wave] = __popcll(bal);
+    __syncthreads();
+    int woff = 0, ctot = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int s = sh[w];
+      if (w < wave) woff += s;
+      ctot += s;
+    }
+    if (nz) {
+      const int pos = base + woff + lanes_below(bal);
+      J_idx[pos] = idx ? idx[t] : t;
+      J_val[pos] = v[t];
+    }
+    if (c == nch - 1 && threadIdx.x == 0) {
+      const int J = base + ctot;
+      int G = (J + kMaxGroups - 1) / kMaxGroups;
+      if (G < 16) G = 16;
+      st->J_cnt = J;
+      st->G = G;
+      st->ngroups = (J + G - 1) / G;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ residual fold
+// part[g][i] = sum over list entries e of group g (ascending) of A[i, J_idx[e]] * J_val[e].
+// Tile = (256*VN rows) x (one group); 16-byte loads down each listed column.
+template <typename T, typename Acc>
+__global__ void __launch_bounds__(256)
+k_fold_partial(const T* __restrict__ A, long long lda, int m, const int* __restrict__ J_idx,
+               const T* __restrict__ J_val, const RoundState* __restrict__ st,
+               Acc* __restrict__ part, long long ldp) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  const int J = st->J_cnt, G = st->G, ng = st->ngroups;
+  const int rows_tile = 256 * VN;
+  const int nrt = (m + rows_tile - 1) / rows_tile;
+  for (int tile = blockIdx.x; tile < nrt * ng; tile += gridDim.x) {
+    const int g = tile / nrt, rt = tile - g * nrt;
+    const int e0 = g * G, e1 = min(J, e0 + G);
+    const int row0 = rt * rows_tile + threadIdx.x * VN;
+    Acc acc[VN];
+#pragma unroll
+    for (int v = 0; v < VN; ++v) acc[v] = (Acc)0;
+    if (row0 + VN <= m) {
+      int e = e0;
+      for (; e + 4 <= e1; e += 4) {
+        VA a[4];
+        Acc d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = J_idx[e + u];
+          d[u] = (Acc)J_val[e + u];
+          a[u] = __builtin_nontemporal_load(
+              reinterpret_cast<const VA*>(A + (size_t)j * lda + row0));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < VN; ++v) acc[v] += (Acc)a[u][v] * d[u];
+      }
+      for (; e < e1; ++e) {
+        const int j = J_idx[e];
+        const Acc d = (Acc)J_val[e];
+        const VA a = __builtin_nontemporal_load(
+            reinterpret_cast<const VA*>(A + (size_t)j * lda + row0));
+#pragma unroll
+        for (int v = 0; v < VN; ++v) acc[v] += (Acc)a[v] * d;
+      }
+    } else if (row0 < m) {
+      for (int e = e0; e < e1; ++e) {
+        const int j = J_idx[e];
+        const Acc d = (Acc)J_val[e];
+        for (int v = 0; v < m - row0; ++v) acc[v] += (Acc)A[(size_t)j * lda + row0 + v] * d;
+      }
+    }
+    if (row0 < m) {
+      Acc* dst = part + (size_t)g * ldp + row0;
+#pragma unroll
+      for (int v = 0; v < VN; ++v)
+        if (row0 + v < m) dst[v] = acc[v];
+    }
+  }
+}
+
+// out[i] = base_scale*base[i] + sum_{g ascending} part[g][i]  (also to out64 when given)
+template <typename TB, typename Acc, typename TO>
+__global__ void __launch_bounds__(256)
+k_fold_reduce(const TB* __restrict__ base, double base_scale, const Acc* __restrict__ part,
+              long long ldp, const RoundState* __restrict__ st, int m, TO* __restrict__ out,
+              double* __restrict__ out64) {
+  const int ng = st->ngroups;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    Acc s = (Acc)(base_scale * (double)base[i]);
+#pragma unroll 8
+    for (int g = 0; g < ng; ++g) s += part[(size_t)g * ldp + i];
+    if (out) out[i] = (TO)s;
+    if (out64) out64[i] = (double)s;
+  }
+}
+
+// ------------------------------------------------------------------ FP64 checks
+// Deterministic block reduction of three doubles (256 threads).
+__device__ __forceinline__ void block_sum3_256(double a, double b, double c, double* dst) {
+  __shared__ double sh[3][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane == 0) {
+    sh[0][wave] = a;
+    sh[1][wave] = b;
+    sh[2][wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 3; ++q) dst[q] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
+  }
+}
+
+// part[3*blk + {0,1,2}] = (sum r_i^2, sum x_j^2, sum h(x_j)) over this block's share.
+template <typename TX, typename TR>
+__global__ void __launch_bounds__(256) k_obj_partial(const TR* __restrict__ r, int m,
+                                                     const TX* __restrict__ x, int n,
+                                                     BRParams bp, double* __restrict__ part) {
+  double sr = 0.0, sx = 0.0, sh = 0.0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const double v = (double)r[i];
+    sr += v * v;
+  }
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+    const double v = (double)x[j];
+    sx += v * v;
+    sh += h_value<double>(v, bp);
+  }
+  block_sum3_256(sr, sx, sh, part + 3 * blockIdx.x);
+}
+
+// out[0] = F = 1/2 sum r^2 - c sum x^2 + lam sum h(x); out[1..3] = the three sums.
+static __global__ void k_obj_final(const double* __restrict__ part, int nparts, double c, double lam,
+                            double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double sr = 0.0, sx = 0.0, sh = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    sr += part[3 * b];
+    sx += part[3 * b + 1];
+    sh += part[3 * b + 2];
+  }
+  out[0] = 0.5 * sr - c * sx + lam * sh;
+  out[1] = sr;
+  out[2] = sx;
+  out[3] = sh;
+}
+
+// Stationarity probe over every coordinate with an FP64 residual: per wave the max of
+// |xh_j - x_j|, the sum of (x_j - y_j)^2 with y the unit-step prox point (M_F) and the
+// count of xh_j != 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_probe(const T* __restrict__ A, long long lda, int m, const double* __restrict__ r64,
+        const T* __restrict__ x, int n, const double* __restrict__ cn2, BRParams bp,
+        double* __restrict__ wmax, double* __restrict__ wsum, int* __restrict__ wcnt) {
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nw = gridDim.x * 4;
+  double mx = 0.0, sm = 0.0;
+  int cnt = 0;
+  for (int j = gw; j < n; j += nw) {
+    const double dot = col_dot<T, double, double, 4>(A + (size_t)j * lda, r64, m, lane);
+    const double xj = (double)x[j];
+    double g = dot - bp.c2 * xj;
+    if (bp.reg) g -= bp.lam * dh_minus<double>(xj, bp);
+    const double q = cn2[j] + bp.tau;
+    const double xh = soft_clip<double>(xj - g / q, bp.lam_eta / q, bp.beta);
+    const double y = soft_clip<double>(xj - g, bp.lam_eta, bp.beta);
+    mx = fmax(mx, fabs(xh - xj));
+    sm += (xj - y) * (xj - y);
+    cnt += (xh != 0.0);
+  }
+  if (lane == 0) {
+    wmax[gw] = mx;
+    wsum[gw] = sm;
+    wcnt[gw] = cnt;
+  }
+}
+
+// out[0] = max, out[1] = sqrt(sum), out[2] = count (fixed summation order).
+static __global__ void k_probe_final(const double* __restrict__ wmax, const double* __restrict__ wsum,
+                              const int* __restrict__ wcnt, int nw, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double mx = 0.0, sm = 0.0;
+  long long cnt = 0;
+  for (int w = 0; w < nw; ++w) {
+    mx = fmax(mx, wmax[w]);
+    sm += wsum[w];
+    cnt += wcnt[w];
+  }
+  out[0] = mx;
+  out[1] = sqrt(sm);
+  out[2] = (double)cnt;
+}
+
+}  // namespace sca

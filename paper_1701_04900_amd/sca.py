@@ -1,0 +1,247 @@
+"""Thin ctypes binding of libsca (include/sca.h): argument marshalling only.
+
+Every function named ``sca_*`` here calls the C entry point of the same name; device
+buffers are torch CUDA tensors (their data pointers are passed), streams are torch's
+current HIP stream.  Nothing here computes: when libsca.so is missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsca.so")
+
+SCA_OK, SCA_EINVAL, SCA_ENOMEM, SCA_EHIP, SCA_ENONFINITE, SCA_ENOTCONV = range(6)
+SCA_F32, SCA_F64 = 0, 1
+SCA_REG_L1, SCA_REG_EXP, SCA_REG_LOG = 0, 1, 2
+SCA_FLAG_PROFILE = 1
+SCA_K_SELECT, SCA_K_GRAD, SCA_K_COMPACT, SCA_K_FOLD, SCA_K_NKINDS = range(5)
+_STATUS = {0: "SCA_OK", 1: "SCA_EINVAL", 2: "SCA_ENOMEM", 3: "SCA_EHIP", 4: "SCA_ENONFINITE",
+           5: "SCA_ENOTCONV"}
+
+
+class SCAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sca_opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("gamma", ctypes.c_double),
+                ("gamma_mu", ctypes.c_double), ("tau", ctypes.c_double),
+                ("select_p", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("instance", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("max_rounds", ctypes.c_int64), ("check_every", ctypes.c_int64),
+                ("refresh_every", ctypes.c_int64), ("tol_rel_obj", ctypes.c_double),
+                ("F_star", ctypes.c_double), ("tol_merit", ctypes.c_double)]
+
+
+class sca_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("rounds", ctypes.c_int64),
+                ("coord_updates", ctypes.c_int64), ("F", ctypes.c_double),
+                ("merit", ctypes.c_double), ("MF", ctypes.c_double),
+                ("rel_err", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("nnz", ctypes.c_int64), ("status", ctypes.c_int32), ("checks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_S = ctypes.c_int
+# name -> (restype, argtypes); the declarations of include/sca.h
+SIGNATURES = {
+    "sca_version": (ctypes.c_char_p, []),
+    "sca_last_error": (ctypes.c_char_p, []),
+    "sca_problem_create_dense": (_S, [ctypes.POINTER(_P), _S, _I64, _I64, _P, _I64, _P, _D, _D,
+                                      _D, ctypes.POINTER(_I64), _I64, _P]),
+    "sca_problem_create_csr": (_S, [ctypes.POINTER(_P), _S, _I64, _I64, _I64, _P, _P, _P, _P,
+                                    _D, _D, _D, ctypes.POINTER(_I64), _I64, _P]),
+    "sca_problem_set_regularizer": (_S, [_P, _S, _D]),
+    "sca_problem_destroy": (None, [_P]),
+    "sca_step": (_S, [_P, ctypes.POINTER(sca_opts), _I64, _I64, _P, _P, _P]),
+    "sca_residual": (_S, [_P, _P, _P, _P]),
+    "sca_select_blocks": (_S, [_P, ctypes.POINTER(sca_opts), _I64, _P, _P]),
+    "sca_philox4x32_10": (_S, [_P, _P, _I64, _P]),
+    "sca_objective": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(_D),
+                           ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64), _P]),
+    "sca_solve": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(sca_stats), _P]),
+    "sca_adjoint": (_S, [_P, ctypes.POINTER(sca_opts), _P, _P, _P, ctypes.POINTER(_D), _D, _I64,
+                         _P]),
+    "sca_profile_get": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D),
+                             _S]),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load libsca.so (raises when it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != SCA_OK:
+        raise SCAError(status, lib().sca_last_error().decode())
+    return status
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(dt):
+    if dt == torch.float32:
+        return SCA_F32
+    if dt == torch.float64:
+        return SCA_F64
+    raise ValueError(f"unsupported dtype {dt}")
+
+
+def make_opts(gamma=0.9, tau=0.0, select_p=1.0, seed=0, instance=0, gamma_mu=0.0, flags=0,
+              max_rounds=0, check_every=10, refresh_every=0, tol_rel_obj=0.0, F_star=0.0,
+              tol_merit=0.0) -> sca_opts:
+    return sca_opts(ctypes.sizeof(sca_opts), gamma, gamma_mu, tau, select_p, seed, instance,
+                    flags, max_rounds, check_every, refresh_every, tol_rel_obj, F_star, tol_merit)
+
+
+# ------------------------------------------------------------------ entry points
+def sca_version():
+    return lib().sca_version().decode()
+
+
+def sca_problem_create_dense(At, m, b, lam, c, beta, block_ptr, stream=None):
+    """At: (n, lda) device tensor (column-major A), b: (m,) device tensor."""
+    n, lda = At.shape
+    bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
+    h = ctypes.c_void_p()
+    _check(lib().sca_problem_create_dense(
+        ctypes.byref(h), _dtype_code(At.dtype), m, n, _dptr(At), lda, _dptr(b), float(lam),
+        float(c), float(beta), bp.ctypes.data_as(ctypes.POINTER(_I64)), len(bp) - 1,
+        _stream(stream)))
+    return h
+
+
+def sca_problem_create_csr(m, n, rowptr, colidx, vals, b, lam, c, beta, block_ptr, stream=None):
+    bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
+    h = ctypes.c_void_p()
+    _check(lib().sca_problem_create_csr(
+        ctypes.byref(h), _dtype_code(vals.dtype), m, n, vals.numel(), _dptr(rowptr),
+        _dptr(colidx), _dptr(vals), _dptr(b), float(lam), float(c), float(beta),
+        bp.ctypes.data_as(ctypes.POINTER(_I64)), len(bp) - 1, _stream(stream)))
+    return h
+
+
+def sca_problem_set_regularizer(h, reg, theta=0.0):
+    _check(lib().sca_problem_set_regularizer(h, int(reg), float(theta)))
+
+
+def sca_problem_destroy(h):
+    lib().sca_problem_destroy(h)
+
+
+def sca_step(h, opts, round_begin, nrounds, x, r, stream=None):
+    _check(lib().sca_step(h, ctypes.byref(opts), int(round_begin), int(nrounds), _dptr(x),
+                          _dptr(r), _stream(stream)))
+
+
+def sca_residual(h, x, r, stream=None):
+    _check(lib().sca_residual(h, _dptr(x), _dptr(r), _stream(stream)))
+
+
+def sca_select_blocks(h, opts, k, mask, stream=None):
+    _check(lib().sca_select_blocks(h, ctypes.byref(opts), int(k), _dptr(mask), _stream(stream)))
+
+
+def sca_philox4x32_10(inp, out, count, stream=None):
+    _check(lib().sca_philox4x32_10(_dptr(inp), _dptr(out), int(count), _stream(stream)))
+
+
+def sca_objective(h, opts, x, stream=None):
+    F, mer, mf, nnz = _D(), _D(), _D(), _I64()
+    _check(lib().sca_objective(h, ctypes.byref(opts), _dptr(x), ctypes.byref(F), ctypes.byref(mer),
+                               ctypes.byref(mf), ctypes.byref(nnz), _stream(stream)))
+    return dict(F=F.value, merit=mer.value, MF=mf.value, nnz=nnz.value)
+
+
+def sca_solve(h, opts, x, stream=None, raise_on_notconv=True):
+    st = sca_stats()
+    st.struct_size = ctypes.sizeof(sca_stats)
+    status = lib().sca_solve(h, ctypes.byref(opts), _dptr(x), ctypes.byref(st), _stream(stream))
+    if status != SCA_OK and not (status == SCA_ENOTCONV and not raise_on_notconv):
+        _check(status)
+    return st.as_dict()
+
+
+def sca_adjoint(h, opts, xstar, xbar, bbar, cg_tol=0.0, cg_maxit=0, stream=None):
+    lb = _D()
+    _check(lib().sca_adjoint(h, ctypes.byref(opts), _dptr(xstar), _dptr(xbar), _dptr(bbar),
+                             ctypes.byref(lb), float(cg_tol), int(cg_maxit), _stream(stream)))
+    return lb.value
+
+
+def sca_profile_get(h, reset=False):
+    ms = (_D * SCA_K_NKINDS)()
+    n = (_I64 * SCA_K_NKINDS)()
+    by = (_D * SCA_K_NKINDS)()
+    _check(lib().sca_profile_get(h, ms, n, by, int(reset)))
+    names = ["select", "grad", "compact", "fold"]
+    return {names[k]: dict(ms=ms[k], launches=n[k], bytes=by[k]) for k in range(SCA_K_NKINDS)}
+
+
+# ------------------------------------------------------------------ convenience holder
+class Problem:
+    """Keeps the borrowed device tensors alive for the lifetime of the library handle."""
+
+    def __init__(self, handle, keep, m, n, dtype):
+        self.handle, self._keep, self.m, self.n, self.dtype = handle, keep, m, n, dtype
+
+    @classmethod
+    def dense(cls, At, m, b, lam, c=0.0, beta=math.inf, block_ptr=None, stream=None):
+        n = At.shape[0]
+        if block_ptr is None:
+            block_ptr = np.arange(n + 1, dtype=np.int64)
+        h = sca_problem_create_dense(At, m, b, lam, c, beta, block_ptr, stream)
+        return cls(h, (At, b), m, n, At.dtype)
+
+    @classmethod
+    def from_workload(cls, w, stream=None):
+        return cls.dense(w.At, w.m, w.b, w.lam, w.c, w.beta, w.block_ptr, stream)
+
+    def close(self):
+        if self.handle is not None:
+            sca_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

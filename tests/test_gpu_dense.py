@@ -1,0 +1,281 @@
+"""GPU parity of the dense hot path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 mode -- iterates, residuals and objectives within 1e-10 relative
+(to max(1, ||.||_inf)); FP32 mode -- objective within 1e-4 relative, iterates within
+1e-3 of max(1, ||x||_inf) (FP32 accumulation drifts from the FP64 trajectory).
+Both sides start from the same seeded inputs; nothing computed on the GPU is fed to
+the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sca_oracle as O
+from paper_1701_04900_amd import inputs, sca
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(w, **kw):
+    return O.Problem(A=w.A_numpy(), b=w.b.double().cpu().numpy(), lam=w.lam, c=w.c,
+                     beta=w.beta, block_ptr=w.block_ptr, **kw)
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b))))) if b.size else 0.0
+
+
+class Run:
+    """GPU state (x, r) of one workload, advanced round by round through sca_step."""
+
+    def __init__(self, w, reg=None, theta=0.0, **optkw):
+        print(f"[gpu] workload {w.name} m={w.m} n={w.n} dtype={w.dtype} p={w.p}", flush=True)
+        self.w = w.to("cuda")
+        self.P = sca.Problem.from_workload(self.w)
+        if reg is not None:
+            sca.sca_problem_set_regularizer(self.P.handle, reg, theta)
+        kw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, instance=w.instance)
+        kw.update(optkw)
+        self.opts = sca.make_opts(**kw)
+        self.x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+        self.r = torch.empty(w.m, dtype=w.dtype, device="cuda")
+        sca.sca_residual(self.P.handle, self.x, self.r)
+        self.k = 0
+
+    def step(self, n=1):
+        sca.sca_step(self.P.handle, self.opts, self.k, n, self.x, self.r)
+        self.k += n
+        torch.cuda.synchronize()
+        return self.x.double().cpu().numpy(), self.r.double().cpu().numpy()
+
+
+def _oracle_run(w, prob, rounds, every, **cfgkw):
+    kw = dict(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed, instance=w.instance)
+    kw.update(cfgkw)
+    cfg = O.RunConfig(**kw)
+    x = np.zeros(w.n)
+    r = O.residual(prob, x)
+    out = []
+    for k in range(0, rounds, every):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k, every)
+        out.append((x.copy(), r.copy()))
+    return out
+
+
+# ---------------------------------------------------------------- RNG / selection
+def test_philox_known_answers_on_device():
+    vecs = [(0, 0, 0, 0, 0, 0, 0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8),
+            (0xFFFFFFFF,) * 6 + (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD),
+            (0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344, 0xA4093822, 0x299F31D0,
+             0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)]
+    inp = torch.tensor([v[:6] for v in vecs], dtype=torch.int64).to(torch.uint32).cuda()
+    out = torch.zeros(len(vecs), 4, dtype=torch.uint32, device="cuda")
+    sca.sca_philox4x32_10(inp, out, len(vecs))
+    torch.cuda.synchronize()
+    got = out.cpu().to(torch.int64).numpy()
+    assert [list(map(int, g)) for g in got] == [list(v[6:]) for v in vecs]
+
+
+@pytest.mark.parametrize("p,seed,inst", [(0.25, 0, 0), (0.1, 12345, 7), (0.5, 2 ** 40 + 3, 1)])
+def test_block_selection_bit_exact(p, seed, inst):
+    w = inputs.lasso_dense_fp32(m=64, n=4000, seed=1)
+    run = Run(w, select_p=p, seed=seed, instance=inst)
+    nb = len(w.block_ptr) - 1
+    mask = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    for k in [0, 1, 17, 2 ** 33 + 5]:
+        sca.sca_select_blocks(run.P.handle, run.opts, k, mask)
+        torch.cuda.synchronize()
+        ref = O.selected_blocks(seed, k, inst, nb, p)
+        assert np.array_equal(mask.cpu().numpy().astype(bool), ref)
+
+
+# ---------------------------------------------------------------- FP64 round by round
+def test_lasso_200x1000_fp64_every_round():
+    """LASSO 200x1000 FP64, scalar blocks, all blocks per round: x and r after every round."""
+    w = inputs.lasso_small_fp64(seed=0)
+    prob = _oracle(w)
+    run = Run(w)
+    ref = _oracle_run(w, prob, 60, 1)
+    worst = 0.0
+    for k in range(60):
+        xg, rg = run.step()
+        xo, ro = ref[k]
+        ex, er = _rel(xg, xo), _rel(rg, ro)
+        worst = max(worst, ex, er)
+        assert ex <= 1e-10 and er <= 1e-10, (k, ex, er)
+    rep = sca.sca_objective(run.P.handle, run.opts, run.x)
+    Fo = O.objective(prob, ref[-1][0])
+    assert abs(rep["F"] - Fo) <= 1e-10 * abs(Fo)
+    print(f"[parity] lasso_200x1000_fp64 worst rel err {worst:.2e} over 60 rounds")
+
+
+@pytest.mark.parametrize("m,n,block,p", [(2000, 10000, 64, 0.25), (1237, 3001, 64, 0.4),
+                                         (517, 2050, 7, 1.0)])
+def test_lasso_fp64_scaled(m, n, block, p):
+    w = inputs.dense_problem(m, n, nnz_frac=0.01, lam_frac=0.01, block=block, p=p,
+                             dtype=torch.float64, seed=3)
+    prob = _oracle(w)
+    run = Run(w)
+    ref = _oracle_run(w, prob, 30, 5)
+    for i, (xo, ro) in enumerate(ref):
+        xg, rg = run.step(5)
+        assert _rel(xg, xo) <= 1e-10, (i, _rel(xg, xo))
+        assert _rel(rg, ro) <= 1e-10, (i, _rel(rg, ro))
+
+
+def test_nonconvex_box_fp64():
+    w = inputs.nonconvex_box_fp32(m=1000, n=5000, dtype=torch.float64, seed=2)
+    assert w.c > 0.4 and w.beta == 1.0
+    prob = _oracle(w)
+    run = Run(w)
+    ref = _oracle_run(w, prob, 40, 10)
+    for xo, ro in ref:
+        xg, rg = run.step(10)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+    assert np.max(np.abs(ref[-1][0])) <= 1.0
+
+
+@pytest.mark.parametrize("reg,code", [("log", sca.SCA_REG_LOG), ("exp", sca.SCA_REG_EXP)])
+def test_dc_regularisers_fp64(reg, code):
+    w = inputs.dense_problem(800, 3000, nnz_frac=0.05, lam_frac=0.02, block=16, p=0.5,
+                             dtype=torch.float64, seed=4)
+    prob = _oracle(w, reg=reg, theta=20.0)
+    run = Run(w, reg=code, theta=20.0)
+    ref = _oracle_run(w, prob, 30, 10)
+    for xo, ro in ref:
+        xg, rg = run.step(10)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+
+
+def test_diminishing_stepsize_fp64():
+    w = inputs.dense_problem(600, 2400, nnz_frac=0.02, lam_frac=0.02, block=32, p=0.5,
+                             dtype=torch.float64, seed=6)
+    prob = _oracle(w)
+    run = Run(w, gamma=1.0, gamma_mu=1e-2)
+    ref = _oracle_run(w, prob, 40, 8, gamma=1.0, gamma_mu=1e-2)
+    for xo, ro in ref:
+        xg, rg = run.step(8)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+
+
+# ---------------------------------------------------------------- FP32
+@pytest.mark.parametrize("m,n", [(2000, 10000), (1237, 3001)])
+def test_lasso_fp32_objective(m, n):
+    w = inputs.lasso_dense_fp32(m=m, n=n, seed=5)
+    prob = _oracle(w)
+    run = Run(w)
+    ref = _oracle_run(w, prob, 40, 10)
+    for xo, ro in ref:
+        xg, rg = run.step(10)
+        Fo = O.objective(prob, xo)
+        Fg = sca.sca_objective(run.P.handle, run.opts, run.x)["F"]
+        assert abs(Fg - Fo) <= 1e-4 * abs(Fo)
+        assert _rel(xg, xo) <= 1e-3
+        print(f"[parity] fp32 {m}x{n} round {run.k}: F rel err {abs(Fg - Fo) / abs(Fo):.2e}, "
+              f"x err {_rel(xg, xo):.2e}")
+
+
+def test_nonconvex_box_fp32_objective():
+    w = inputs.nonconvex_box_fp32(m=1000, n=5000, seed=8)
+    prob = _oracle(w)
+    run = Run(w)
+    ref = _oracle_run(w, prob, 30, 10)
+    for xo, _ in ref:
+        run.step(10)
+        Fo = O.objective(prob, xo)
+        Fg = sca.sca_objective(run.P.handle, run.opts, run.x)["F"]
+        assert abs(Fg - Fo) <= 1e-4 * abs(Fo)
+
+
+# ---------------------------------------------------------------- checks and reports
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_residual_objective_merit_at_a_seeded_point(dtype):
+    w = inputs.dense_problem(1500, 4000, nnz_frac=0.05, lam_frac=0.05, c_frac=0.2, beta=1.5,
+                             block=32, p=0.5, dtype=dtype, seed=9)
+    prob = _oracle(w)
+    xs = w.x_true.clamp(-1.5, 1.5).to(dtype)  # a seeded point from the generator
+    run = Run(w)
+    xd = xs.cuda()
+    r = torch.empty(w.m, dtype=dtype, device="cuda")
+    sca.sca_residual(run.P.handle, xd, r)
+    rep = sca.sca_objective(run.P.handle, run.opts, xd)
+    xo = xs.double().numpy()
+    ro = O.residual(prob, xo)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    assert _rel(r.double().cpu().numpy(), ro) <= tol
+    Fo = O.objective(prob, xo)
+    assert abs(rep["F"] - Fo) <= 1e-12 * abs(Fo)  # FP64 accumulation in both modes
+    assert abs(rep["merit"] - O.merit(prob, xo, w.tau)) <= 1e-10 * max(1, rep["merit"])
+    assert abs(rep["MF"] - O.stationarity_MF(prob, xo)) <= 1e-10 * max(1, rep["MF"])
+    assert rep["nnz"] == O.nnz_best_response(prob, xo, w.tau)
+
+
+def test_solve_reaches_tolerance_and_matches_oracle_F_star():
+    w = inputs.dense_problem(300, 1200, nnz_frac=0.05, lam_frac=0.05, block=8, p=0.5,
+                             dtype=torch.float64, seed=10)
+    prob = _oracle(w)
+    Fs, _ = O.estimate_F_star(prob, O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed))
+    run = Run(w, max_rounds=20000, check_every=10, tol_rel_obj=1e-10, F_star=Fs)
+    st = sca.sca_solve(run.P.handle, run.opts, run.x)
+    assert st["status"] == sca.SCA_OK
+    assert st["rel_err"] <= 1e-10
+    assert st["coord_updates"] > 0 and st["rounds"] % 10 == 0
+    out = O.solve(prob, O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed),
+                  check_every=10, F_star=Fs, tol_rel_obj=1e-10, max_rounds=20000)
+    # the stopping check may land one check apart when F crosses the threshold within rounding
+    assert abs(out["rounds"] - st["rounds"]) <= 10
+    if out["rounds"] == st["rounds"]:
+        assert out["updates"] == st["coord_updates"]
+
+
+# ---------------------------------------------------------------- determinism / resume / errors
+def test_determinism_and_resume_bitwise():
+    w = inputs.lasso_dense_fp32(m=1500, n=6000, seed=11)
+    a = Run(w)
+    a.step(25)
+    b = Run(w)
+    b.step(25)
+    c = Run(w)
+    c.step(10)
+    c.step(15)
+    assert torch.equal(a.x, b.x) and torch.equal(a.r, b.r)
+    assert torch.equal(a.x, c.x) and torch.equal(a.r, c.r)
+
+
+def test_error_paths():
+    w = inputs.lasso_small_fp64(seed=0)
+    run = Run(w)
+    bad = sca.make_opts(gamma=1.5, tau=w.tau)
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_step(run.P.handle, bad, 0, 1, run.x, run.r)
+    assert e.value.status == sca.SCA_EINVAL
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_step(run.P.handle, sca.make_opts(select_p=0.0), 0, 1, run.x, run.r)
+    assert e.value.status == sca.SCA_EINVAL
+    # divergence: no proximal term, every block, unit step -> non-finite objective
+    div = sca.make_opts(gamma=1.0, tau=0.0, select_p=1.0, max_rounds=5000, check_every=10)
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_solve(run.P.handle, div, run.x)
+    assert e.value.status == sca.SCA_ENONFINITE
+    # budget exhausted
+    run2 = Run(w)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, max_rounds=20, check_every=10,
+                      tol_rel_obj=1e-14, F_star=1.0)
+    st = sca.sca_solve(run2.P.handle, o, run2.x, raise_on_notconv=False)
+    assert st["status"] == sca.SCA_ENOTCONV and st["rounds"] == 20
+    # a zero column with tau = 0
+    At = w.At.clone()
+    At[3] = 0
+    P = sca.Problem.dense(At.cuda(), w.m, w.b.cuda(), w.lam, block_ptr=w.block_ptr)
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_step(P.handle, sca.make_opts(tau=0.0), 0, 1, run.x, run.r)
+    assert e.value.status == sca.SCA_EINVAL
+    # NaN in b
+    b = w.b.clone()
+    b[5] = math.nan
+    with pytest.raises(sca.SCAError) as e:
+        sca.Problem.dense(w.At.cuda(), w.m, b.cuda(), w.lam, block_ptr=w.block_ptr)
+    assert e.value.status == sca.SCA_EINVAL
