@@ -86,6 +86,7 @@ typedef struct {
   size_t struct_size;    /* = sizeof(sca_stats)                                          */
   int64_t rounds;        /* rounds run                                                    */
   int64_t coord_updates; /* sum over rounds of the drawn coordinates                      */
+  int64_t moved_updates; /* sum over rounds of the coordinates that moved (columns folded) */
   double F;              /* final objective with a freshly computed residual (FP64 acc.)  */
   double merit;          /* final ||xh(x) - x||_inf                                       */
   double MF;             /* final ||M_F(x)||_2 (unit-step prox residual, Section 3)      */

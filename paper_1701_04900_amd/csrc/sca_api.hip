@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -88,6 +89,24 @@ BRParams sca::make_brparams(const sca_problem* p, double tau) {
   bp.eta = p->eta;
   bp.reg = p->reg;
   return bp;
+}
+
+// Launch-shape overrides (used by the tuning sweeps): SCA_GRAD_UNROLL in {4, 8, 16},
+// SCA_GRAD_WG_PER_CU in [1, 16].
+void sca::apply_launch_env(sca_problem* p) {
+  if (const char* e = getenv("SCA_GRAD_UNROLL")) {
+    const int u = atoi(e);
+    if (u == 1 || u == 2 || u == 4 || u == 8 || u == 16) p->grad_unroll = u;
+  }
+  if (const char* e = getenv("SCA_GRAD_KIND")) p->grad_kind = atoi(e) == 1 ? 1 : 0;
+  if (const char* e = getenv("SCA_GRAD_COLS")) {
+    const int c = atoi(e);
+    if (c == 2 || c == 4 || c == 8) p->grad_cols = c;
+  }
+  if (const char* e = getenv("SCA_GRAD_WG_PER_CU")) {
+    const int w = atoi(e);
+    if (w >= 1 && w <= 16) p->grad_wg_per_cu = w;
+  }
 }
 
 // ------------------------------------------------------------------ problem lifetime
@@ -235,6 +254,7 @@ extern "C" sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtyp
   p->beta = beta;
   p->nblocks = nblocks;
   p->ncu = device_cu_count();
+  apply_launch_env(p);
   if ((st = alloc_workspace(p, block_ptr)) != SCA_OK ||
       (st = finish_create(p, (hipStream_t)stream)) != SCA_OK) {
     free_workspace(p);
@@ -331,9 +351,37 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
   // Algorithmic bytes of the gradient pass: m*sizeof(T) per drawn coordinate (known on
   // the host only in profiling mode, where it is computed from the expected count).
   prof_begin(p, s, SCA_K_GRAD);
-  hipLaunchKernelGGL((k_grad_br<T, 8>), dim3(p->ncu * p->grad_wg_per_cu), dim3(256), 0, s,
-                     (const T*)p->A, (long long)p->lda, m, (const T*)r, x, p->d_cn2,
-                     p->d_sel_cols, p->d_state, (T*)p->d_dx_sel, bp);
+  const dim3 ggrid(p->ncu * p->grad_wg_per_cu);
+#define GRAD_LAUNCH(UU)                                                                     \
+  hipLaunchKernelGGL((k_grad_br<T, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,           \
+                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,         \
+                     p->d_state, (T*)p->d_dx_sel, bp)
+#define GRAD_WG_LAUNCH(CC, UU)                                                              \
+  hipLaunchKernelGGL((k_grad_br_wg<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,      \
+                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
+                     p->d_state, (T*)p->d_dx_sel, bp)
+  if (p->grad_kind == 1) {
+    if (p->grad_cols == 2 && p->grad_unroll == 4)
+      GRAD_WG_LAUNCH(2, 4);
+    else if (p->grad_cols == 4 && p->grad_unroll == 4)
+      GRAD_WG_LAUNCH(4, 4);
+    else if (p->grad_cols == 8 && p->grad_unroll == 2)
+      GRAD_WG_LAUNCH(8, 2);
+    else if (p->grad_cols == 8 && p->grad_unroll == 1)
+      GRAD_WG_LAUNCH(8, 1);
+    else if (p->grad_cols == 4 && p->grad_unroll == 1)
+      GRAD_WG_LAUNCH(4, 1);
+    else
+      GRAD_WG_LAUNCH(4, 2);
+  } else if (p->grad_unroll == 4) {
+    GRAD_LAUNCH(4);
+  } else if (p->grad_unroll == 16) {
+    GRAD_LAUNCH(16);
+  } else {
+    GRAD_LAUNCH(8);
+  }
+#undef GRAD_LAUNCH
+#undef GRAD_WG_LAUNCH
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_COMPACT);
   const int nch = (n + kChunk - 1) / kChunk;
@@ -343,7 +391,7 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
                      (const int*)S_ptr, p->d_chunk_cnt);
   hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s,
                      (const T*)p->d_dx_sel, (const int*)p->d_sel_cols, (const int*)S_ptr,
-                     (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val, p->d_state);
+                     (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val, p->d_state, 1);
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_FOLD);
   constexpr int VN = V16<T>::N;
@@ -369,7 +417,7 @@ static void launch_residual_dense(sca_problem* p, const T* x, T* r_out, hipStrea
                      p->d_chunk_cnt);
   hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s, x, (const int*)nullptr,
                      (const int*)N_ptr, (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val,
-                     p->d_state);
+                     p->d_state, 0);
   constexpr int VN = V16<T>::N;
   const int nrt = (m + 256 * VN - 1) / (256 * VN);
   const int fgrid = std::max(1, std::min(nrt * kMaxGroups, 8 * p->ncu));
@@ -390,7 +438,7 @@ static void launch_objective(sca_problem* p, const T* x, const void* r, bool r_i
   else
     hipLaunchKernelGGL((k_obj_partial<T, T>), dim3(p->obj_blocks), dim3(256), 0, s,
                        (const T*)r, (int)p->m, x, (int)p->n, bp, p->d_obj_part);
-  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, s, (const double*)p->d_obj_part,
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(256), 0, s, (const double*)p->d_obj_part,
                      p->obj_blocks, p->c, p->lam, out_dev);
 }
 
@@ -404,7 +452,7 @@ static void launch_probe(sca_problem* p, const T* x, const BRParams& bp, double*
                        (long long)p->lda, (int)p->m, (const double*)p->d_r64, x, (int)p->n,
                        (const double*)p->d_cn2, bp, p->d_wmax, p->d_wsum, p->d_wcnt);
   }
-  hipLaunchKernelGGL(k_probe_final, dim3(1), dim3(64), 0, s, (const double*)p->d_wmax,
+  hipLaunchKernelGGL(k_probe_final, dim3(1), dim3(256), 0, s, (const double*)p->d_wmax,
                      (const double*)p->d_wsum, (const int*)p->d_wcnt, p->probe_waves, out_dev);
 }
 
@@ -567,6 +615,7 @@ extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_
     return set_error(SCA_EINVAL, "tol_rel_obj needs a finite nonzero F_star");
   hipStream_t s = (hipStream_t)stream;
   const BRParams bp = make_brparams(p, o->tau);
+  p->profiling = (o->flags & SCA_FLAG_PROFILE) != 0;
   void* r = p->d_rtmp;  // running residual in the dtype (library-owned)
   // r^0 = A x^0 - b (FP64 accumulation); round counter and step from round 0
   init_round_state(p, o, 0, s);
@@ -588,6 +637,7 @@ extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_
     if (hipMemcpyAsync(&F, p->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return set_error(SCA_EHIP, "solve: %s", hipGetErrorString(hipGetLastError()));
+    prof_collect(p);
     if (!std::isfinite(F)) {
       result = SCA_ENONFINITE;
       break;
@@ -609,6 +659,7 @@ extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_
       break;
     }
   }
+  p->profiling = false;
   if (o->max_rounds == 0 || (o->tol_rel_obj <= 0.0 && o->tol_merit <= 0.0 && result == SCA_ENOTCONV))
     result = SCA_OK;  // no tolerance asked: running the budget is success
   double Ff = NAN, mer = NAN, mf = NAN;
@@ -616,14 +667,15 @@ extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_
   if (result != SCA_ENONFINITE) {
     if ((st = report(p, o, x, &Ff, &mer, &mf, &nnz, s)) != SCA_OK) return st;
   }
-  int64_t updates = 0;
-  if (hipMemcpyAsync(&updates, (char*)p->d_state + offsetof(RoundState, coord_updates),
-                     sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  int64_t counters[2] = {0, 0};  // coord_updates, moved_updates (adjacent in RoundState)
+  if (hipMemcpyAsync(counters, (char*)p->d_state + offsetof(RoundState, coord_updates),
+                     2 * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return set_error(SCA_EHIP, "solve: %s", hipGetErrorString(hipGetLastError()));
   if (stats) {
     stats->rounds = k;
-    stats->coord_updates = updates;
+    stats->coord_updates = counters[0];
+    stats->moved_updates = counters[1];
     stats->F = Ff;
     stats->merit = mer;
     stats->MF = mf;

@@ -22,7 +22,10 @@ struct sca_problem {
   std::vector<int64_t> block_ptr_host;
   double cn2_min = 0;
   int ncu = 256;
-  int grad_wg_per_cu = 2;
+  int grad_wg_per_cu = 2;  // gradient kernel: 256-thread workgroups per CU
+  int grad_unroll = 2;     // gradient kernel: 16-byte loads (wave) / row steps (wg) in flight
+  int grad_kind = 1;       // 0: one wave per column, 1: one workgroup per group of columns
+  int grad_cols = 8;       // workgroup variant: columns per group
 
   // sparse A (library-owned CSC: colptr n+1, rowidx nnz, vals nnz)
   bool sparse = false;
@@ -77,6 +80,7 @@ double gamma_at_round(double g0, double mu, long long k);
 uint64_t selection_threshold(double p);
 void prof_begin(sca_problem* p, hipStream_t s, int kind);
 void prof_end(sca_problem* p, hipStream_t s, double bytes);
+void apply_launch_env(sca_problem* p);
 void init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begin, hipStream_t s);
 void residual_any(sca_problem* p, const void* x, void* r_out, hipStream_t s);
 

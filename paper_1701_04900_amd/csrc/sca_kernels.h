@@ -10,6 +10,7 @@ namespace sca {
 struct RoundState {
   long long k;              // index of the next round to run
   long long coord_updates;  // sum of drawn coordinates over the rounds run
+  long long moved_updates;  // sum of moved coordinates (columns folded) over the rounds run
   double gamma_cur;         // step of the round in flight
   double gamma_next;        // step of the following round
   double gamma_mu;          // diminishing-rule parameter (0 = fixed step)
@@ -135,7 +136,10 @@ static __global__ void k_count_nonfinite(const T* __restrict__ v, long long len,
 static __global__ void k_init_state(RoundState* st, long long k, double gamma, double mu, int n_all,
                              int reset_updates) {
   st->k = k;
-  if (reset_updates) st->coord_updates = 0;
+  if (reset_updates) {
+    st->coord_updates = 0;
+    st->moved_updates = 0;
+  }
   st->gamma_cur = gamma;
   st->gamma_next = gamma;
   st->gamma_mu = mu;
@@ -148,26 +152,58 @@ static __global__ void k_init_state(RoundState* st, long long k, double gamma, d
 }
 
 // ------------------------------------------------------------------ S.1: block draw
-// One 1024-thread workgroup: each thread owns a contiguous range of blocks, the drawn
-// coordinates are listed in ascending order.  Also advances the round counter and the
+// One 1024-thread workgroup.  Each thread owns a contiguous range of blocks; two block
+// scans give every drawn block its rank and its first output position, so the drawn
+// coordinates are listed in ascending order.  When the drawn blocks fit the shared list
+// (kSelList), waves then write each drawn block's coordinates with coalesced stores;
+// otherwise every thread writes its own blocks.  Also advances the round counter and the
 // step of the diminishing rule, and resets the gradient work counter.
+constexpr int kSelList = 4096;
 static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* __restrict__ bp,
-                                                 uint64_t seed, uint32_t inst, uint64_t T,
-                                                 RoundState* __restrict__ st,
-                                                 int* __restrict__ sel_cols) {
+                                                        uint64_t seed, uint32_t inst, uint64_t T,
+                                                        RoundState* __restrict__ st,
+                                                        int* __restrict__ sel_cols) {
   __shared__ int sh[17];
+  __shared__ int s_blk[kSelList];
+  __shared__ int s_off[kSelList];
   const long long k = st->k;
   const int per = (nblocks + 1023) / 1024;
   const int b0 = min(nblocks, (int)threadIdx.x * per);
   const int b1 = min(nblocks, b0 + per);
-  int cnt = 0;
-  for (int i = b0; i < b1; ++i)
-    if (block_drawn((uint32_t)i, (uint64_t)k, inst, seed, T)) cnt += bp[i + 1] - bp[i];
-  int total;
-  int off = block_exclusive_scan_1024(cnt, sh, &total);
+  int cnt = 0, nsel = 0;
+  uint32_t mask = 0;  // drawn flags of the first 32 owned blocks
   for (int i = b0; i < b1; ++i) {
     if (block_drawn((uint32_t)i, (uint64_t)k, inst, seed, T)) {
-      for (int c = bp[i]; c < bp[i + 1]; ++c) sel_cols[off++] = c;
+      cnt += bp[i + 1] - bp[i];
+      ++nsel;
+      if (i - b0 < 32) mask |= 1u << (i - b0);
+    }
+  }
+  int total, nsel_total;
+  int off = block_exclusive_scan_1024(cnt, sh, &total);
+  int rank = block_exclusive_scan_1024(nsel, sh, &nsel_total);
+  const bool listed = nsel_total <= kSelList && per <= 32;
+  if (listed) {
+    for (int i = b0; i < b1; ++i) {
+      if (mask & (1u << (i - b0))) {
+        s_blk[rank] = i;
+        s_off[rank] = off;
+        ++rank;
+        off += bp[i + 1] - bp[i];
+      }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q < nsel_total; q += 16) {
+      const int i = s_blk[q], o = s_off[q];
+      const int c0 = bp[i], len = bp[i + 1] - c0;
+      for (int c = lane; c < len; c += 64) sel_cols[o + c] = c0 + c;
+    }
+  } else {
+    for (int i = b0; i < b1; ++i) {
+      if (block_drawn((uint32_t)i, (uint64_t)k, inst, seed, T)) {
+        for (int c = bp[i]; c < bp[i + 1]; ++c) sel_cols[off++] = c;
+      }
     }
   }
   if (threadIdx.x == 0) {
@@ -231,6 +267,104 @@ k_grad_br(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r
   }
 }
 
+// Workgroup variant: 256 threads walk down C drawn columns together (16-byte loads; one
+// 4 KiB contiguous segment per column and step), reusing each residual load across the C
+// columns; U row steps are kept in flight.  Groups of C consecutive drawn coordinates are
+// handed out by an integer counter.  The per-thread partial dots are reduced in a fixed
+// order (wave butterfly, then the four waves in order) before the best response.
+template <typename T, int C, int U>
+__global__ void __launch_bounds__(256)
+k_grad_br_wg(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
+             T* __restrict__ x, const double* __restrict__ cn2, const int* __restrict__ sel_cols,
+             RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  constexpr int ROWS = 256 * VN;  // rows per step of the workgroup
+  __shared__ T red[4][C];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int S = st->S_cnt;
+  const int ngroups = (S + C - 1) / C;
+  const T gamma = (T)st->gamma_cur;
+  const int nfull = m / ROWS;  // steps where every thread holds VN valid rows
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&st->work_ctr, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= ngroups) break;
+    const int t0 = item * C;
+    const T* col[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int t = min(t0 + c, S - 1);  // a short last group repeats its last column
+      col[c] = A + (size_t)sel_cols[t] * lda;
+    }
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = (T)0;
+    const int row_t = threadIdx.x * VN;
+    int step = 0;
+    for (; step + U <= nfull; step += U) {
+      VA a[U][C], rv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int row = (step + u) * ROWS + row_t;
+        rv[u] = *reinterpret_cast<const VA*>(r + row);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          a[u][c] = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) acc[c] += a[u][c][e] * rv[u][e];
+    }
+    for (; step < nfull; ++step) {
+      const int row = step * ROWS + row_t;
+      const VA rv = *reinterpret_cast<const VA*>(r + row);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const VA a = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row));
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[c] += a[e] * rv[e];
+      }
+    }
+    {  // ragged tail: rows nfull*ROWS .. m-1
+      const int row = nfull * ROWS + row_t;
+      for (int e = 0; e < VN; ++e) {
+        if (row + e < m) {
+          const T rr = r[row + e];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] += col[c][row + e] * rr;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const T v = wave_sum(acc[c]);
+      if (lane == 0) red[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < C && t0 + (int)threadIdx.x < S) {
+      const int c = threadIdx.x;
+      const int t = t0 + c;
+      const int j = sel_cols[t];
+      const T dot = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      const T xj = x[j];
+      T g = dot - (T)bp.c2 * xj;
+      if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+      const T q = (T)(cn2[j] + bp.tau);
+      const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
+      const T d = gamma * (xh - xj);
+      x[j] = xj + d;
+      dx_sel[t] = d;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ compaction
 // Two passes over v[0..N): per-chunk nonzero counts, then an ordered scatter of
 // (index, value) for the nonzero entries.  N is read from device memory.
@@ -262,7 +396,8 @@ template <typename T>
 __global__ void __launch_bounds__(1024)
 k_compact_scatter(const T* __restrict__ v, const int* __restrict__ idx,
                   const int* __restrict__ N_ptr, const int* __restrict__ chunk_cnt,
-                  int* __restrict__ J_idx, T* __restrict__ J_val, RoundState* __restrict__ st) {
+                  int* __restrict__ J_idx, T* __restrict__ J_val, RoundState* __restrict__ st,
+                  int count_moved) {
   __shared__ int sh[17];
   __shared__ int sh_base;
   const int N = *N_ptr;
@@ -303,6 +438,7 @@ k_compact_scatter(const T* __restrict__ v, const int* __restrict__ idx,
       int G = (J + kMaxGroups - 1) / kMaxGroups;
       if (G < 16) G = 16;
       st->J_cnt = J;
+      if (count_moved) st->moved_updates += J;
       st->G = G;
       st->ngroups = (J + G - 1) / G;
     }
@@ -426,19 +562,25 @@ __global__ void __launch_bounds__(256) k_obj_partial(const TR* __restrict__ r, i
 }
 
 // out[0] = F = 1/2 sum r^2 - c sum x^2 + lam sum h(x); out[1..3] = the three sums.
-static __global__ void k_obj_final(const double* __restrict__ part, int nparts, double c, double lam,
-                            double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+// 256 threads: thread i sums parts i, i+256, ... in order, then a fixed-order tree.
+static __global__ void __launch_bounds__(256) k_obj_final(const double* __restrict__ part,
+                                                          int nparts, double c, double lam,
+                                                          double* __restrict__ out) {
   double sr = 0.0, sx = 0.0, sh = 0.0;
-  for (int b = 0; b < nparts; ++b) {
+  for (int b = threadIdx.x; b < nparts; b += 256) {
     sr += part[3 * b];
     sx += part[3 * b + 1];
     sh += part[3 * b + 2];
   }
-  out[0] = 0.5 * sr - c * sx + lam * sh;
-  out[1] = sr;
-  out[2] = sx;
-  out[3] = sh;
+  __shared__ double res[3];
+  block_sum3_256(sr, sx, sh, res);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = 0.5 * res[0] - c * res[1] + lam * res[2];
+    out[1] = res[0];
+    out[2] = res[1];
+    out[3] = res[2];
+  }
 }
 
 // Stationarity probe over every coordinate with an FP64 residual: per wave the max of
@@ -473,20 +615,29 @@ k_probe(const T* __restrict__ A, long long lda, int m, const double* __restrict_
   }
 }
 
-// out[0] = max, out[1] = sqrt(sum), out[2] = count (fixed summation order).
-static __global__ void k_probe_final(const double* __restrict__ wmax, const double* __restrict__ wsum,
-                              const int* __restrict__ wcnt, int nw, double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
-  double mx = 0.0, sm = 0.0;
-  long long cnt = 0;
-  for (int w = 0; w < nw; ++w) {
+// out[0] = max, out[1] = sqrt(sum), out[2] = count (fixed summation order, 256 threads).
+static __global__ void __launch_bounds__(256) k_probe_final(const double* __restrict__ wmax,
+                                                            const double* __restrict__ wsum,
+                                                            const int* __restrict__ wcnt, int nw,
+                                                            double* __restrict__ out) {
+  double mx = 0.0, sm = 0.0, cnt = 0.0;
+  for (int w = threadIdx.x; w < nw; w += 256) {
     mx = fmax(mx, wmax[w]);
     sm += wsum[w];
-    cnt += wcnt[w];
+    cnt += (double)wcnt[w];
   }
-  out[0] = mx;
-  out[1] = sqrt(sm);
-  out[2] = (double)cnt;
+  __shared__ double shm[4];
+  __shared__ double res[3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double wm = wave_max(mx);
+  if (lane == 0) shm[wave] = wm;
+  block_sum3_256(sm, cnt, 0.0, res);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = fmax(fmax(shm[0], shm[1]), fmax(shm[2], shm[3]));
+    out[1] = sqrt(res[0]);
+    out[2] = res[1];
+  }
 }
 
 }  // namespace sca

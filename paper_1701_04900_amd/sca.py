@@ -43,7 +43,8 @@ class sca_opts(ctypes.Structure):
 
 class sca_stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("rounds", ctypes.c_int64),
-                ("coord_updates", ctypes.c_int64), ("F", ctypes.c_double),
+                ("coord_updates", ctypes.c_int64), ("moved_updates", ctypes.c_int64),
+                ("F", ctypes.c_double),
                 ("merit", ctypes.c_double), ("MF", ctypes.c_double),
                 ("rel_err", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("nnz", ctypes.c_int64), ("status", ctypes.c_int32), ("checks", ctypes.c_int32)]
