@@ -59,7 +59,7 @@ sca_status sca::validate_opts(const sca_opts* o) {
   return SCA_OK;
 }
 
-static int device_cu_count() {
+int sca::device_cu_count() {
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -110,9 +110,9 @@ void sca::apply_launch_env(sca_problem* p) {
 }
 
 // ------------------------------------------------------------------ problem lifetime
-static sca_status common_checks(sca_dtype dtype, int64_t m, int64_t n, const void* b,
-                                double lambda, double c, double beta,
-                                const int64_t* block_ptr, int64_t nblocks) {
+sca_status sca::validate_problem_args(sca_dtype dtype, int64_t m, int64_t n, const void* b,
+                                      double lambda, double c, double beta,
+                                      const int64_t* block_ptr, int64_t nblocks) {
   if (dtype != SCA_F32 && dtype != SCA_F64) return set_error(SCA_EINVAL, "unknown dtype");
   if (m <= 0 || n <= 0 || m > INT32_MAX / 2 || n > INT32_MAX / 2)
     return set_error(SCA_EINVAL, "m, n must lie in [1, 2^30)");
@@ -136,7 +136,7 @@ static sca_status common_checks(sca_dtype dtype, int64_t m, int64_t n, const voi
   return SCA_OK;
 }
 
-static sca_status alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
+sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
   const int n = (int)p->n;
   const size_t es = p->esize;
   const int nch = (n + kChunk - 1) / kChunk + 1;
@@ -154,7 +154,7 @@ static sca_status alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
   ALLOC(p->d_J_idx, sizeof(int) * n);
   ALLOC(p->d_J_val, es * n);
   p->ldp = (p->m + 63) / 64 * 64;
-  ALLOC(p->d_part, sizeof(double) * kMaxGroups * p->ldp);
+  ALLOC(p->d_part, p->sparse ? 64 : sizeof(double) * kMaxGroups * p->ldp);
   ALLOC(p->d_r64, sizeof(double) * p->ldp);
   ALLOC(p->d_rtmp, es * p->ldp);
   ALLOC(p->d_scal, sizeof(double) * 64);
@@ -175,7 +175,7 @@ static sca_status alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
   return SCA_OK;
 }
 
-static void free_workspace(sca_problem* p) {
+void sca::free_workspace(sca_problem* p) {
   void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state, p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
                   p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
                   p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
@@ -233,7 +233,7 @@ extern "C" sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtyp
                                                int64_t nblocks, void* stream) {
   if (!out) return set_error(SCA_EINVAL, "out is NULL");
   *out = nullptr;
-  sca_status st = common_checks(dtype, m, n, b, lambda, c, beta, block_ptr, nblocks);
+  sca_status st = validate_problem_args(dtype, m, n, b, lambda, c, beta, block_ptr, nblocks);
   if (st != SCA_OK) return st;
   const size_t es = dtype == SCA_F32 ? 4 : 8;
   if (!A) return set_error(SCA_EINVAL, "A is NULL");

@@ -72,6 +72,12 @@ namespace sca {
 sca_status set_error(sca_status st, const char* fmt, ...);
 sca_status validate_opts(const sca_opts* o);
 sca_status dev_alloc(void** p, size_t bytes);
+int device_cu_count();
+sca_status validate_problem_args(sca_dtype dtype, int64_t m, int64_t n, const void* b,
+                                 double lambda, double c, double beta, const int64_t* block_ptr,
+                                 int64_t nblocks);
+sca_status alloc_workspace(sca_problem* p, const int64_t* block_ptr);
+void free_workspace(sca_problem* p);
 sca_status finish_create(sca_problem* p, hipStream_t s);
 sca_status report(sca_problem* p, const sca_opts* o, const void* x, double* F, double* merit,
                   double* MF, int64_t* nnz, hipStream_t s);

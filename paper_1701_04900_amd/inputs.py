@@ -181,3 +181,118 @@ def nonconvex_box_fp32(m=10000, n=50000, seed=0, device="cpu", dtype=torch.float
                          c_frac=0.5, beta=1.0, block=32, p=0.25, gamma=0.9, dtype=dtype,
                          seed=seed, device=device,
                          name=f"ncvx_box_{m}x{n}_{str(dtype).split('.')[-1]}")
+
+
+# --------------------------------------------------------------------------------------
+# Sparse workloads (CSR)
+# --------------------------------------------------------------------------------------
+@dataclass
+class SparseWorkload:
+    name: str
+    m: int
+    n: int
+    rowptr: torch.Tensor      # (m+1,) int64
+    colidx: torch.Tensor      # (nnz,) int32, ascending inside each row
+    vals: torch.Tensor        # (nnz,) storage dtype
+    b: torch.Tensor           # (m,) storage dtype
+    x_true: torch.Tensor      # (n,) float64
+    lam: float
+    c: float
+    beta: float
+    tau: float
+    block_ptr: np.ndarray
+    p: float
+    gamma: float
+    seed: int
+    instance: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dtype(self):
+        return self.vals.dtype
+
+    @property
+    def nnz(self):
+        return int(self.vals.numel())
+
+    def scipy_csr(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.vals.double().cpu().numpy(), self.colidx.cpu().numpy(),
+                              self.rowptr.cpu().numpy()), shape=(self.m, self.n))
+
+    def to(self, device):
+        return SparseWorkload(self.name, self.m, self.n, self.rowptr.to(device),
+                              self.colidx.to(device), self.vals.to(device), self.b.to(device),
+                              self.x_true.to(device), self.lam, self.c, self.beta, self.tau,
+                              self.block_ptr, self.p, self.gamma, self.seed, self.instance,
+                              dict(self.meta))
+
+
+def sparse_problem(m: int, n: int, *, per_col: int, nnz_frac: float, amp=(1.0, 2.0),
+                   sigma: float = 0.01, lam_frac: float = 0.01, block: int = 256,
+                   p: float = 0.1, gamma: float = 0.9, dtype=torch.float32, seed: int = 0,
+                   device="cpu", tau=None, name: str = "sparse") -> SparseWorkload:
+    """CSR A with exactly ``per_col`` distinct uniform rows in every column, N(0,1) values,
+    columns scaled to unit norm in float64; x*, b, lam, tau as for the dense recipe."""
+    if per_col > m:
+        raise ValueError("per_col must not exceed m")
+    g = _gen(device, seed)
+    rows = torch.randint(0, m, (n, per_col), generator=g, device=device)
+    for _ in range(64):  # redraw repeated rows inside a column until all are distinct
+        rows, _ = torch.sort(rows, dim=1)
+        dup = torch.zeros_like(rows, dtype=torch.bool)
+        dup[:, 1:] = rows[:, 1:] == rows[:, :-1]
+        nd = int(dup.sum())
+        if nd == 0:
+            break
+        rows[dup] = torch.randint(0, m, (nd,), generator=g, device=device)
+    else:
+        raise RuntimeError("could not draw distinct rows")
+    vals = torch.randn(n, per_col, dtype=torch.float64, generator=g, device=device)
+    vals /= torch.linalg.vector_norm(vals, dim=1, keepdim=True)
+    vals_st = vals.to(dtype)
+    s = int(round(nnz_frac * n))
+    supp = torch.randperm(n, generator=g, device=device)[:s]
+    mag = amp[0] + (amp[1] - amp[0]) * torch.rand(s, dtype=torch.float64, generator=g, device=device)
+    sgn = torch.where(torch.rand(s, dtype=torch.float64, generator=g, device=device) < 0.5, -1.0, 1.0)
+    x_true = torch.zeros(n, dtype=torch.float64, device=device)
+    x_true[supp] = sgn * mag
+    noise = torch.randn(m, dtype=torch.float64, generator=g, device=device)
+    # b = A_stored x_true + sigma e, summed on the host in a fixed order (numpy add.at)
+    sup = supp.cpu().numpy()
+    contrib = (vals_st[supp].double() * x_true[supp][:, None]).cpu().numpy()
+    b64 = sigma * noise.cpu().numpy()
+    np.add.at(b64, rows[supp].cpu().numpy().ravel(), contrib.ravel())
+    b = torch.from_numpy(b64).to(dtype).to(device)
+    # A^T b and column norms of the stored values
+    atb = (vals_st.double() * b.double()[rows]).sum(dim=1)
+    cn = (vals_st.double() ** 2).sum(dim=1)
+    lam = lam_frac * float(atb.abs().max())
+    cn_min, cn_max = float(cn.min()), float(cn.max())
+    if tau is None:
+        tau = tau_heuristic(cn_min, cn_max, m, n, p)
+    # CSR: entries ordered by (row, column)
+    cols = torch.arange(n, device=device, dtype=torch.int64)[:, None].expand(n, per_col)
+    key = rows.reshape(-1) * n + cols.reshape(-1)
+    order = torch.argsort(key)
+    r_sorted = rows.reshape(-1)[order]
+    colidx = cols.reshape(-1)[order].to(torch.int32)
+    v_sorted = vals_st.reshape(-1)[order]
+    counts = torch.bincount(r_sorted, minlength=m)
+    rowptr = torch.zeros(m + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    del key, order, rows, cols, vals
+    return SparseWorkload(name, m, n, rowptr, colidx.contiguous(), v_sorted.contiguous(), b,
+                          x_true, float(lam), 0.0, math.inf, float(tau), block_partition(n, block),
+                          float(p), float(gamma), int(seed), 0,
+                          dict(colnorm2_min=cn_min, colnorm2_max=cn_max, nnz_true=s))
+
+
+def sparse_lasso_fp32(m=100000, n=1000000, per_col=100, seed=0, device="cpu",
+                      dtype=torch.float32):
+    """Sparse LASSO, CSR 100000 x 1000000 (default), 0.1% density (100 uniform distinct rows
+    per column), N(0,1) values, unit columns, 0.5% nonzeros +-[1,2], sigma 0.01,
+    lam = 0.01||A^T b||_inf, blocks of 256, 10% of blocks per round, gamma 0.9."""
+    return sparse_problem(m, n, per_col=per_col, nnz_frac=0.005, amp=(1.0, 2.0), sigma=0.01,
+                          lam_frac=0.01, block=256, p=0.1, gamma=0.9, dtype=dtype, seed=seed,
+                          device=device, name=f"sparse_lasso_{m}x{n}_{str(dtype).split('.')[-1]}")

@@ -233,7 +233,18 @@ class Problem:
         return cls(h, (At, b), m, n, At.dtype)
 
     @classmethod
+    def csr(cls, m, n, rowptr, colidx, vals, b, lam, c=0.0, beta=math.inf, block_ptr=None,
+            stream=None):
+        if block_ptr is None:
+            block_ptr = np.arange(n + 1, dtype=np.int64)
+        h = sca_problem_create_csr(m, n, rowptr, colidx, vals, b, lam, c, beta, block_ptr, stream)
+        return cls(h, (b,), m, n, vals.dtype)  # the CSR may be released after create
+
+    @classmethod
     def from_workload(cls, w, stream=None):
+        if hasattr(w, "rowptr"):
+            return cls.csr(w.m, w.n, w.rowptr, w.colidx, w.vals, w.b, w.lam, w.c, w.beta,
+                           w.block_ptr, stream)
         return cls.dense(w.At, w.m, w.b, w.lam, w.c, w.beta, w.block_ptr, stream)
 
     def close(self):

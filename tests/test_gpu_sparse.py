@@ -1,0 +1,124 @@
+"""GPU parity of the sparse (CSR in, CSC inside) path against the FP64 CPU oracle
+(scipy.sparse matrices on the oracle side).  Tolerances as for the dense path."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sca_oracle as O
+from paper_1701_04900_amd import inputs, sca
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
+
+
+def _oracle(w, **kw):
+    return O.Problem(A=w.scipy_csr().tocsc(), b=w.b.double().cpu().numpy(), lam=w.lam, c=w.c,
+                     beta=w.beta, block_ptr=w.block_ptr, **kw)
+
+
+class Run:
+    def __init__(self, w, **optkw):
+        print(f"[gpu] sparse workload {w.name} m={w.m} n={w.n} nnz={w.nnz} dtype={w.dtype}",
+              flush=True)
+        self.w = w.to("cuda")
+        self.P = sca.Problem.from_workload(self.w)
+        kw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+        kw.update(optkw)
+        self.opts = sca.make_opts(**kw)
+        self.x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+        self.r = torch.empty(w.m, dtype=w.dtype, device="cuda")
+        sca.sca_residual(self.P.handle, self.x, self.r)
+        self.k = 0
+
+    def step(self, n=1):
+        sca.sca_step(self.P.handle, self.opts, self.k, n, self.x, self.r)
+        self.k += n
+        torch.cuda.synchronize()
+        return self.x.double().cpu().numpy(), self.r.double().cpu().numpy()
+
+
+def _oracle_traj(w, prob, rounds, every):
+    cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
+    x = np.zeros(w.n)
+    r = O.residual(prob, x)
+    out = []
+    for k in range(0, rounds, every):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k, every)
+        out.append((x.copy(), r.copy()))
+    return out
+
+
+@pytest.mark.parametrize("m,n,per_col,p", [(2000, 20000, 20, 0.1), (1531, 7001, 9, 0.3)])
+def test_sparse_fp64_parity(m, n, per_col, p):
+    w = inputs.sparse_problem(m, n, per_col=per_col, nnz_frac=0.005, lam_frac=0.01, block=256,
+                              p=p, dtype=torch.float64, seed=1)
+    prob = _oracle(w)
+    run = Run(w)
+    for xo, ro in _oracle_traj(w, prob, 40, 5):
+        xg, rg = run.step(5)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+
+
+def test_sparse_fp32_objective():
+    w = inputs.sparse_lasso_fp32(m=4000, n=40000, per_col=40, seed=2)
+    prob = _oracle(w)
+    run = Run(w)
+    for xo, _ in _oracle_traj(w, prob, 60, 15):
+        run.step(15)
+        Fo = O.objective(prob, xo)
+        Fg = sca.sca_objective(run.P.handle, run.opts, run.x)["F"]
+        assert abs(Fg - Fo) <= 1e-4 * abs(Fo)
+
+
+def test_sparse_report_at_seeded_point_and_determinism():
+    w = inputs.sparse_problem(3000, 12000, per_col=30, nnz_frac=0.02, lam_frac=0.05, block=128,
+                              p=0.5, dtype=torch.float64, seed=3)
+    prob = _oracle(w)
+    run = Run(w)
+    xs = w.x_true.clone()
+    xd = xs.cuda()
+    r = torch.empty(w.m, dtype=torch.float64, device="cuda")
+    sca.sca_residual(run.P.handle, xd, r)
+    rep = sca.sca_objective(run.P.handle, run.opts, xd)
+    xo = xs.numpy()
+    assert _rel(r.cpu().numpy(), O.residual(prob, xo)) <= 1e-13
+    Fo = O.objective(prob, xo)
+    assert abs(rep["F"] - Fo) <= 1e-12 * abs(Fo)
+    assert abs(rep["merit"] - O.merit(prob, xo, w.tau)) <= 1e-10 * max(1, rep["merit"])
+    assert abs(rep["MF"] - O.stationarity_MF(prob, xo)) <= 1e-10 * max(1, rep["MF"])
+    assert rep["nnz"] == O.nnz_best_response(prob, xo, w.tau)
+    a = Run(w)
+    a.step(20)
+    b = Run(w)
+    b.step(7)
+    b.step(13)
+    assert torch.equal(a.x, b.x) and torch.equal(a.r, b.r)
+
+
+def test_sparse_rejects_bad_csr():
+    w = inputs.sparse_problem(500, 2000, per_col=5, nnz_frac=0.01, block=64, p=0.5,
+                              dtype=torch.float64, seed=4).to("cuda")
+    bad = w.colidx.clone()
+    bad[7] = w.n  # out of range
+    with pytest.raises(sca.SCAError) as e:
+        sca.Problem.csr(w.m, w.n, w.rowptr, bad, w.vals, w.b, w.lam, block_ptr=w.block_ptr)
+    assert e.value.status == sca.SCA_EINVAL
+    dup = w.colidx.clone()
+    r0, r1 = int(w.rowptr[0]), int(w.rowptr[1])
+    assert r1 - r0 >= 2
+    dup[r0 + 1] = dup[r0]  # repeated (row, column)
+    with pytest.raises(sca.SCAError) as e:
+        sca.Problem.csr(w.m, w.n, w.rowptr, dup, w.vals, w.b, w.lam, block_ptr=w.block_ptr)
+    assert e.value.status == sca.SCA_EINVAL
+    rp = w.rowptr.clone()
+    rp[-1] += 1
+    with pytest.raises(sca.SCAError) as e:
+        sca.Problem.csr(w.m, w.n, rp, w.colidx, w.vals, w.b, w.lam, block_ptr=w.block_ptr)
+    assert e.value.status == sca.SCA_EINVAL
