@@ -186,6 +186,71 @@ sca_status sca_adjoint(sca_problem* p, const sca_opts* opts, const void* xstar_d
 sca_status sca_profile_get(sca_problem* p, double* ms_host, int64_t* launches_host,
                            double* bytes_host, int reset);
 
+/* ------------------------------------------------------------------------------------
+ * Batched form: many dense instances of uneven size advance together, one round of every
+ * active instance per launch sequence (a block-diagonal problem).  Instance k follows the
+ * trajectory of the plain path run with opts.instance = item.instance: the batch shares
+ * gamma, gamma_mu, select_p and seed from sca_opts; tau, lambda, c, beta and F_star are
+ * per instance.  x and r of the batch are concatenations laid out as sca_batch_layout
+ * reports (r offsets padded to 16 bytes; padding entries are never read).
+ * ------------------------------------------------------------------------------------ */
+typedef struct sca_batch sca_batch; /* opaque, owned by the library */
+
+typedef struct {
+  size_t struct_size;            /* = sizeof(sca_batch_item)                            */
+  int64_t m, n;                  /* rows and columns of this instance                   */
+  const void* A_dev;             /* column-major, as for sca_problem_create_dense; borrowed */
+  int64_t lda;
+  const void* b_dev;             /* m elements; copied into the batch at create          */
+  double lambda, c, beta;        /* as for sca_problem_create_dense                      */
+  double tau;                    /* proximal weight of this instance                     */
+  double F_star;                 /* reference optimum for tol_rel_obj (0 = unknown)      */
+  const int64_t* block_ptr_host; /* nblocks+1 offsets, copied                            */
+  int64_t nblocks;
+  uint32_t instance;             /* Philox counter word 3 of this instance               */
+  uint32_t reserved;
+} sca_batch_item;
+
+/* Create a batch over count instances (items_host: count entries).  Validation as for the
+ * dense create, per item.  Synchronises 'stream'. */
+sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t count,
+                            const sca_batch_item* items_host, void* stream);
+
+/* Release the batch (the A matrices stay with the caller).  NULL is a no-op. */
+void sca_batch_destroy(sca_batch* batch);
+
+/* Offsets (count+1 entries each, host) of every instance in the concatenated x and r. */
+sca_status sca_batch_layout(sca_batch* batch, int64_t* x_offsets_host, int64_t* r_offsets_host);
+
+/* Regulariser shared by every instance (as sca_problem_set_regularizer). */
+sca_status sca_batch_set_regularizer(sca_batch* batch, sca_reg reg, double theta);
+
+/* Replace the per-instance F_star (count entries, host). */
+sca_status sca_batch_set_fstar(sca_batch* batch, const double* F_star_host);
+
+/* r_all <- A_k x_k - b_k for every instance, FP64 accumulation.  Stream-ordered. */
+sca_status sca_batch_residual(sca_batch* batch, const void* x_all_dev, void* r_all_dev,
+                              void* stream);
+
+/* Rounds round_begin .. round_begin+nrounds-1 of every instance, in place (parity path;
+ * r_all must equal A x - b on entry).  Stream-ordered. */
+sca_status sca_batch_step(sca_batch* batch, const sca_opts* opts, int64_t round_begin,
+                          int64_t nrounds, void* x_all_dev, void* r_all_dev, void* stream);
+
+/* Solve every instance from x_all (in: x^0, out: x).  Rounds run in graph launches of
+ * check_every rounds followed by a fresh FP64 residual and, per instance, the test
+ * (F - F_star)/|F_star| <= tol_rel_obj; a converged instance stops drawing blocks.  stats
+ * (count entries, may be NULL) receive per-instance results.  Synchronises 'stream';
+ * returns SCA_ENOTCONV when an instance ran out of max_rounds. */
+sca_status sca_batch_solve(sca_batch* batch, const sca_opts* opts, void* x_all_dev,
+                           sca_stats* stats_host, void* stream);
+
+/* Per-instance F, merit, ||M_F|| and nnz(xh) with fresh residuals (arrays of count
+ * entries, any may be NULL).  Synchronises 'stream'. */
+sca_status sca_batch_objective(sca_batch* batch, const sca_opts* opts, const void* x_all_dev,
+                               double* F_host, double* merit_host, double* MF_host,
+                               int64_t* nnz_host, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

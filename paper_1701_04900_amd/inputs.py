@@ -296,3 +296,29 @@ def sparse_lasso_fp32(m=100000, n=1000000, per_col=100, seed=0, device="cpu",
     return sparse_problem(m, n, per_col=per_col, nnz_frac=0.005, amp=(1.0, 2.0), sigma=0.01,
                           lam_frac=0.01, block=256, p=0.1, gamma=0.9, dtype=dtype, seed=seed,
                           device=device, name=f"sparse_lasso_{m}x{n}_{str(dtype).split('.')[-1]}")
+
+
+# --------------------------------------------------------------------------------------
+# Batches of uneven dense instances
+# --------------------------------------------------------------------------------------
+def batch_lasso(count: int, m_range=(500, 8000), n_ratio: int = 5, nnz_frac: float = 0.02,
+                lam_range=(1e-3, 1e-1), block: int = 64, p: float = 0.25, gamma: float = 0.9,
+                sigma: float = 0.01, c_frac: float = 0.0, beta: float = math.inf,
+                dtype=torch.float32, seed: int = 0, device="cpu"):
+    """``count`` LASSO instances: m_k uniform in m_range (inclusive), n_k = n_ratio m_k,
+    lam_k = lam_range[0] (lam_range[1]/lam_range[0])^(k/(count-1)) ||A_k^T b_k||_inf
+    (log-spaced), x* with nnz_frac nonzeros +-[1,2]; instance k uses seed*1000003 + k and
+    Philox instance word k."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(int(seed))
+    ms = torch.randint(m_range[0], m_range[1] + 1, (count,), generator=g).tolist()
+    out = []
+    for k, m in enumerate(ms):
+        t = k / (count - 1) if count > 1 else 0.0
+        lam_frac = lam_range[0] * (lam_range[1] / lam_range[0]) ** t
+        w = dense_problem(m, n_ratio * m, nnz_frac=nnz_frac, amp=(1.0, 2.0), sigma=sigma,
+                          lam_frac=lam_frac, c_frac=c_frac, beta=beta, block=block, p=p,
+                          gamma=gamma, dtype=dtype, seed=int(seed) * 1000003 + k, device=device,
+                          name=f"batch{k}_{m}x{n_ratio * m}", instance=k)
+        out.append(w)
+    return out

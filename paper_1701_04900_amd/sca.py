@@ -53,6 +53,15 @@ class sca_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "struct_size"}
 
 
+class sca_batch_item(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("A_dev", ctypes.c_void_p), ("lda", ctypes.c_int64), ("b_dev", ctypes.c_void_p),
+                ("lambda_", ctypes.c_double), ("c", ctypes.c_double), ("beta", ctypes.c_double),
+                ("tau", ctypes.c_double), ("F_star", ctypes.c_double),
+                ("block_ptr_host", ctypes.POINTER(ctypes.c_int64)), ("nblocks", ctypes.c_int64),
+                ("instance", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _D = ctypes.c_double
@@ -78,6 +87,17 @@ SIGNATURES = {
                          _P]),
     "sca_profile_get": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D),
                              _S]),
+    "sca_batch_create": (_S, [ctypes.POINTER(_P), _S, _I64, ctypes.POINTER(sca_batch_item), _P]),
+    "sca_batch_destroy": (None, [_P]),
+    "sca_batch_layout": (_S, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "sca_batch_set_regularizer": (_S, [_P, _S, _D]),
+    "sca_batch_set_fstar": (_S, [_P, ctypes.POINTER(_D)]),
+    "sca_batch_residual": (_S, [_P, _P, _P, _P]),
+    "sca_batch_step": (_S, [_P, ctypes.POINTER(sca_opts), _I64, _I64, _P, _P, _P]),
+    "sca_batch_solve": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(sca_stats), _P]),
+    "sca_batch_objective": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(_D),
+                                 ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64),
+                                 _P]),
 }
 
 _LIB = None
@@ -250,6 +270,102 @@ class Problem:
     def close(self):
         if self.handle is not None:
             sca_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ batched form
+def sca_batch_create(items, dtype, stream=None):
+    """items: list of dicts with keys m, n, At (device (n, lda)), b (device), lam, c, beta,
+    tau, F_star, block_ptr (int64 array), instance."""
+    arr = (sca_batch_item * len(items))()
+    keep = []
+    for k, it in enumerate(items):
+        bp = np.ascontiguousarray(it["block_ptr"], dtype=np.int64)
+        keep.append(bp)
+        arr[k] = sca_batch_item(ctypes.sizeof(sca_batch_item), it["m"], it["n"],
+                                it["At"].data_ptr(), it["At"].shape[1], it["b"].data_ptr(),
+                                float(it["lam"]), float(it.get("c", 0.0)),
+                                float(it.get("beta", math.inf)), float(it["tau"]),
+                                float(it.get("F_star", 0.0)),
+                                bp.ctypes.data_as(ctypes.POINTER(_I64)), len(bp) - 1,
+                                int(it.get("instance", k)), 0)
+    h = ctypes.c_void_p()
+    _check(lib().sca_batch_create(ctypes.byref(h), _dtype_code(dtype), len(items), arr,
+                                  _stream(stream)))
+    return h
+
+
+def sca_batch_destroy(h):
+    lib().sca_batch_destroy(h)
+
+
+def sca_batch_layout(h, K):
+    xo = (_I64 * (K + 1))()
+    ro = (_I64 * (K + 1))()
+    _check(lib().sca_batch_layout(h, xo, ro))
+    return np.array(xo[:], dtype=np.int64), np.array(ro[:], dtype=np.int64)
+
+
+def sca_batch_set_regularizer(h, reg, theta=0.0):
+    _check(lib().sca_batch_set_regularizer(h, int(reg), float(theta)))
+
+
+def sca_batch_set_fstar(h, F_star):
+    a = np.ascontiguousarray(F_star, dtype=np.float64)
+    _check(lib().sca_batch_set_fstar(h, a.ctypes.data_as(ctypes.POINTER(_D))))
+
+
+def sca_batch_residual(h, x_all, r_all, stream=None):
+    _check(lib().sca_batch_residual(h, _dptr(x_all), _dptr(r_all), _stream(stream)))
+
+
+def sca_batch_step(h, opts, round_begin, nrounds, x_all, r_all, stream=None):
+    _check(lib().sca_batch_step(h, ctypes.byref(opts), int(round_begin), int(nrounds),
+                                _dptr(x_all), _dptr(r_all), _stream(stream)))
+
+
+def sca_batch_solve(h, opts, x_all, K, stream=None, raise_on_notconv=True):
+    st = (sca_stats * K)()
+    for k in range(K):
+        st[k].struct_size = ctypes.sizeof(sca_stats)
+    status = lib().sca_batch_solve(h, ctypes.byref(opts), _dptr(x_all), st, _stream(stream))
+    if status != SCA_OK and not (status == SCA_ENOTCONV and not raise_on_notconv):
+        _check(status)
+    return [st[k].as_dict() for k in range(K)]
+
+
+def sca_batch_objective(h, opts, x_all, K, stream=None):
+    F, mer, mf, nnz = (_D * K)(), (_D * K)(), (_D * K)(), (_I64 * K)()
+    _check(lib().sca_batch_objective(h, ctypes.byref(opts), _dptr(x_all), F, mer, mf, nnz,
+                                     _stream(stream)))
+    return dict(F=np.array(F[:]), merit=np.array(mer[:]), MF=np.array(mf[:]),
+                nnz=np.array(nnz[:]))
+
+
+class Batch:
+    """Batch handle plus the per-instance device tensors it borrows."""
+
+    def __init__(self, workloads, F_star=None, stream=None):
+        self.K = len(workloads)
+        self.dtype = workloads[0].dtype
+        items = []
+        for k, w in enumerate(workloads):
+            items.append(dict(m=w.m, n=w.n, At=w.At, b=w.b, lam=w.lam, c=w.c, beta=w.beta,
+                              tau=w.tau, F_star=0.0 if F_star is None else F_star[k],
+                              block_ptr=w.block_ptr, instance=w.instance))
+        self._keep = [(w.At, w.b) for w in workloads]
+        self.handle = sca_batch_create(items, self.dtype, stream)
+        self.xoff, self.roff = sca_batch_layout(self.handle, self.K)
+
+    def close(self):
+        if self.handle is not None:
+            sca_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
