@@ -133,6 +133,10 @@ sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype, int64_t m,
 /* Select the regulariser (default SCA_REG_L1).  theta > 0 for EXP and LOG. */
 sca_status sca_problem_set_regularizer(sca_problem* p, sca_reg reg, double theta);
 
+/* Replace the right-hand side (borrowed, m elements) and lambda of a problem, e.g. for a
+ * lambda sweep or a finite-difference probe.  Checks that b is finite; synchronises. */
+sca_status sca_problem_update_rhs(sca_problem* p, const void* b_dev, double lambda, void* stream);
+
 /* Release the problem and its workspace (A and b stay with the caller).  NULL is a no-op. */
 void sca_problem_destroy(sca_problem* p);
 
@@ -244,6 +248,18 @@ sca_status sca_batch_step(sca_batch* batch, const sca_opts* opts, int64_t round_
  * returns SCA_ENOTCONV when an instance ran out of max_rounds. */
 sca_status sca_batch_solve(sca_batch* batch, const sca_opts* opts, void* x_all_dev,
                            sca_stats* stats_host, void* stream);
+
+/* Replace every instance's right-hand side (b_all_dev in the r layout; valid rows are
+ * copied) and lambda (lambda_host, count entries).  Synchronises 'stream'. */
+sca_status sca_batch_update_rhs(sca_batch* batch, const void* b_all_dev, const double* lambda_host,
+                                void* stream);
+
+/* The adjoint of sca_adjoint for every instance at once (x*, xbar in the x layout, bbar in
+ * the r layout, lambar_host: count entries).  Each instance runs its own conjugate
+ * gradients with its own scalars and stopping test.  Synchronises 'stream'. */
+sca_status sca_batch_adjoint(sca_batch* batch, const sca_opts* opts, const void* xstar_all_dev,
+                             const void* xbar_all_dev, void* bbar_all_dev, double* lambar_host,
+                             double cg_tol, int64_t cg_maxit, void* stream);
 
 /* Per-instance F, merit, ||M_F|| and nnz(xh) with fresh residuals (arrays of count
  * entries, any may be NULL).  Synchronises 'stream'. */

@@ -182,6 +182,8 @@ void sca::free_workspace(sca_problem* p) {
                   p->csc_colptr, p->csc_rowidx, p->csc_vals, p->csr_tmp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  adjoint_release(p->adj);
+  p->adj = nullptr;
   for (auto& e : p->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -278,6 +280,31 @@ extern "C" sca_status sca_problem_set_regularizer(sca_problem* p, sca_reg reg, d
   p->reg = (int)reg;
   p->theta = theta;
   p->eta = reg == SCA_REG_EXP ? theta : theta / std::log1p(theta);
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_problem_update_rhs(sca_problem* p, const void* b, double lambda,
+                                             void* stream) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  if (!b || ((uintptr_t)b) % p->esize) return set_error(SCA_EINVAL, "b is NULL or misaligned");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda))
+    return set_error(SCA_EINVAL, "lambda must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemsetAsync(p->d_int, 0, sizeof(int), s) != hipSuccess)
+    return set_error(SCA_EHIP, "memset failed");
+  if (p->dtype == SCA_F32)
+    hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(64), dim3(256), 0, s, (const float*)b,
+                       (long long)p->m, p->d_int);
+  else
+    hipLaunchKernelGGL(k_count_nonfinite<double>, dim3(64), dim3(256), 0, s, (const double*)b,
+                       (long long)p->m, p->d_int);
+  int bad = 0;
+  if (hipMemcpyAsync(&bad, p->d_int, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SCA_EHIP, "finite check failed");
+  if (bad) return set_error(SCA_EINVAL, "b holds NaN or Inf");
+  p->b = b;
+  p->lam = lambda;
   return SCA_OK;
 }
 

@@ -14,37 +14,12 @@
 #include <new>
 #include <vector>
 
-#include "sca_internal.h"
+#include "sca_batch_internal.h"
 
 using namespace sca;
 
 namespace {
 
-constexpr int kBC = 8;          // columns per gradient work item
-constexpr int kBMaxGroups = 32;  // fold: max column groups per instance and round
-
-struct BInst {
-  const void* A;
-  long long lda;
-  int m, n;
-  int row_off, col_off, blk_off, nblk;
-  double lam, c, beta, tau, F_star;
-  unsigned int inst_id;
-  int pad;
-};
-
-struct BItem {
-  int pos;   // first position in the drawn list
-  int cnt;   // columns (<= kBC), all of one block
-  int inst;  // instance
-};
-
-struct BState {
-  RoundState rs;  // round counter, step, totals, compaction results
-  int items;      // work items of the round in flight
-  int tiles;      // fold tiles of the fold in flight
-  int pad[2];
-};
 
 __device__ __forceinline__ int upper_idx(const int* __restrict__ off, int K, int v) {
   // largest k in [0, K) with off[k] <= v (off ascending, off[0] = 0)
@@ -548,50 +523,6 @@ __global__ void k_bcolnorm2(const BInst* __restrict__ inst, const int* __restric
 
 }  // namespace
 
-// ------------------------------------------------------------------ host object
-struct sca_batch {
-  int dtype = SCA_F32;
-  size_t esize = 4;
-  int K = 0;
-  long long Mtot = 0, Ntot = 0;
-  int Btot = 0;
-  int ncu = 256;
-  int reg = 0;
-  double theta = 0, eta = 1;
-  std::vector<BInst> hinst;
-  std::vector<long long> xoff, roff;
-  // device
-  BInst* d_inst = nullptr;
-  int *d_blk_inst = nullptr, *d_blk_col0 = nullptr, *d_blk_len = nullptr, *d_blk_cols = nullptr;
-  int *d_row_inst = nullptr, *d_col_inst = nullptr;
-  int *d_chunk_a = nullptr, *d_chunk_b = nullptr, *d_chunk_cnt = nullptr;
-  double* d_cn2 = nullptr;
-  void* d_b = nullptr;
-  double* d_r64 = nullptr;
-  void* d_rrun = nullptr;  // running residual of batch_solve
-  int* d_sel_cols = nullptr;
-  BItem* d_items = nullptr;
-  void* d_dx_sel = nullptr;
-  int* d_J_idx = nullptr;
-  void* d_J_val = nullptr;
-  int *d_J_lo = nullptr, *d_Jn = nullptr, *d_G = nullptr, *d_ng = nullptr, *d_nrt = nullptr,
-      *d_tile_off = nullptr;
-  double* d_part = nullptr;
-  BState* d_state = nullptr;
-  int* d_active = nullptr;
-  long long* d_done = nullptr;
-  long long* d_upd = nullptr;
-  double* d_F = nullptr;
-  double *d_cm = nullptr, *d_cs = nullptr;
-  int* d_cz = nullptr;
-  double* d_pr = nullptr;
-  hipStream_t cap = nullptr;
-  hipGraphExec_t graph = nullptr;
-  int graph_rounds = 0;
-  const void* graph_x = nullptr;
-  double graph_tol = 0;
-};
-
 namespace {
 
 void batch_free(sca_batch* B) {
@@ -605,6 +536,8 @@ void batch_free(sca_batch* B) {
     if (q) (void)hipFree(q);
   if (B->graph) (void)hipGraphExecDestroy(B->graph);
   if (B->cap) (void)hipStreamDestroy(B->cap);
+  adjoint_release(B->adj);
+  B->adj = nullptr;
 }
 
 int* N_total_ptr(sca_batch* B) { return (int*)((char*)B->d_state + offsetof(RoundState, n_all)); }
@@ -725,6 +658,13 @@ sca_status check_hip(const char* what) {
 }
 
 }  // namespace
+
+void sca::batch_fresh_residual(sca_batch* B, const void* x, hipStream_t s) {
+  if (B->dtype == SCA_F32)
+    batch_residual<float>(B, (const float*)x, (float*)nullptr, s);
+  else
+    batch_residual<double>(B, (const double*)x, (double*)nullptr, s);
+}
 
 // ------------------------------------------------------------------ public entry points
 extern "C" sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t count,
@@ -1114,6 +1054,28 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
     }
   }
   if (notconv) return set_error(SCA_ENOTCONV, "%d instances did not reach the tolerance", notconv);
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_batch_update_rhs(sca_batch* B, const void* b_all, const double* lambda,
+                                           void* stream) {
+  if (!B || !b_all || !lambda) return set_error(SCA_EINVAL, "NULL argument");
+  for (int k = 0; k < B->K; ++k)
+    if (!(lambda[k] >= 0.0) || !std::isfinite(lambda[k]))
+      return set_error(SCA_EINVAL, "lambda[%d] must be finite and >= 0", k);
+  hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < B->K; ++k) {  // copy the valid rows only; padding stays zero
+    const size_t off = B->esize * (size_t)B->roff[k];
+    if (hipMemcpyAsync((char*)B->d_b + off, (const char*)b_all + off,
+                       B->esize * (size_t)B->hinst[k].m, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return set_error(SCA_EHIP, "rhs copy failed");
+    B->hinst[k].lam = lambda[k];
+  }
+  if (hipMemcpyAsync(B->d_inst, B->hinst.data(), sizeof(BInst) * B->K, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SCA_EHIP, "descriptor update failed");
   return SCA_OK;
 }
 

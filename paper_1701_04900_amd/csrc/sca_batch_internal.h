@@ -1,0 +1,90 @@
+// Internal declarations of the batched engine, shared with the adjoint.
+#pragma once
+#include <vector>
+
+#include "sca_internal.h"
+
+struct sca_batch;
+
+namespace sca {
+
+constexpr int kBC = 8;           // columns per gradient work item
+constexpr int kBMaxGroups = 32;  // fold: max column groups per instance and round
+
+struct BInst {
+  const void* A;
+  long long lda;
+  int m, n;
+  int row_off, col_off, blk_off, nblk;
+  double lam, c, beta, tau, F_star;
+  unsigned int inst_id;
+  int pad;
+};
+
+struct BItem {
+  int pos;   // first position in the drawn list
+  int cnt;   // columns (<= kBC), all of one block
+  int inst;  // instance
+};
+
+struct BState {
+  RoundState rs;  // round counter, step, totals, compaction results
+  int items;      // work items of the round in flight
+  int tiles;      // fold tiles of the fold in flight
+  int pad[2];
+};
+
+
+// FP64 residual A_k x_k - b_k of every instance into the batch's r64 (stream-ordered).
+void batch_fresh_residual(sca_batch* B, const void* x, hipStream_t s);
+
+}  // namespace sca
+
+// Host object of a batch.
+struct sca_batch {
+  using BInst = sca::BInst;
+  using BItem = sca::BItem;
+  using BState = sca::BState;
+  int dtype = SCA_F32;
+  size_t esize = 4;
+  int K = 0;
+  long long Mtot = 0, Ntot = 0;
+  int Btot = 0;
+  int ncu = 256;
+  int reg = 0;
+  double theta = 0, eta = 1;
+  std::vector<BInst> hinst;
+  std::vector<long long> xoff, roff;
+  // device
+  BInst* d_inst = nullptr;
+  int *d_blk_inst = nullptr, *d_blk_col0 = nullptr, *d_blk_len = nullptr, *d_blk_cols = nullptr;
+  int *d_row_inst = nullptr, *d_col_inst = nullptr;
+  int *d_chunk_a = nullptr, *d_chunk_b = nullptr, *d_chunk_cnt = nullptr;
+  double* d_cn2 = nullptr;
+  void* d_b = nullptr;
+  double* d_r64 = nullptr;
+  void* d_rrun = nullptr;  // running residual of batch_solve
+  int* d_sel_cols = nullptr;
+  BItem* d_items = nullptr;
+  void* d_dx_sel = nullptr;
+  int* d_J_idx = nullptr;
+  void* d_J_val = nullptr;
+  int *d_J_lo = nullptr, *d_Jn = nullptr, *d_G = nullptr, *d_ng = nullptr, *d_nrt = nullptr,
+      *d_tile_off = nullptr;
+  double* d_part = nullptr;
+  BState* d_state = nullptr;
+  int* d_active = nullptr;
+  long long* d_done = nullptr;
+  long long* d_upd = nullptr;
+  double* d_F = nullptr;
+  double *d_cm = nullptr, *d_cs = nullptr;
+  int* d_cz = nullptr;
+  double* d_pr = nullptr;
+  sca_adj_cache* adj = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_rounds = 0;
+  const void* graph_x = nullptr;
+  double graph_tol = 0;
+};
+

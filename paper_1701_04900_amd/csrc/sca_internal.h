@@ -8,6 +8,8 @@
 #include "../../include/sca.h"
 #include "sca_kernels.h"
 
+struct sca_adj_cache;  // adjoint workspace (created on first use)
+
 struct sca_problem {
   // problem data
   int dtype = SCA_F32;
@@ -57,6 +59,8 @@ struct sca_problem {
   double* d_wsum = nullptr;
   int* d_wcnt = nullptr;
 
+  sca_adj_cache* adj = nullptr;
+
   // profiling
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -89,6 +93,8 @@ void prof_end(sca_problem* p, hipStream_t s, double bytes);
 void apply_launch_env(sca_problem* p);
 void init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begin, hipStream_t s);
 void residual_any(sca_problem* p, const void* x, void* r_out, hipStream_t s);
+
+void adjoint_release(sca_adj_cache* c);
 
 // sparse (CSC) path
 void launch_colnorm2_csc(sca_problem* p, hipStream_t s);

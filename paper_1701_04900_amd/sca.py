@@ -75,6 +75,7 @@ SIGNATURES = {
     "sca_problem_create_csr": (_S, [ctypes.POINTER(_P), _S, _I64, _I64, _I64, _P, _P, _P, _P,
                                     _D, _D, _D, ctypes.POINTER(_I64), _I64, _P]),
     "sca_problem_set_regularizer": (_S, [_P, _S, _D]),
+    "sca_problem_update_rhs": (_S, [_P, _P, _D, _P]),
     "sca_problem_destroy": (None, [_P]),
     "sca_step": (_S, [_P, ctypes.POINTER(sca_opts), _I64, _I64, _P, _P, _P]),
     "sca_residual": (_S, [_P, _P, _P, _P]),
@@ -95,6 +96,9 @@ SIGNATURES = {
     "sca_batch_residual": (_S, [_P, _P, _P, _P]),
     "sca_batch_step": (_S, [_P, ctypes.POINTER(sca_opts), _I64, _I64, _P, _P, _P]),
     "sca_batch_solve": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(sca_stats), _P]),
+    "sca_batch_update_rhs": (_S, [_P, _P, ctypes.POINTER(_D), _P]),
+    "sca_batch_adjoint": (_S, [_P, ctypes.POINTER(sca_opts), _P, _P, _P, ctypes.POINTER(_D), _D,
+                               _I64, _P]),
     "sca_batch_objective": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(_D),
                                  ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64),
                                  _P]),
@@ -182,6 +186,10 @@ def sca_problem_create_csr(m, n, rowptr, colidx, vals, b, lam, c, beta, block_pt
 
 def sca_problem_set_regularizer(h, reg, theta=0.0):
     _check(lib().sca_problem_set_regularizer(h, int(reg), float(theta)))
+
+
+def sca_problem_update_rhs(h, b, lam, stream=None):
+    _check(lib().sca_problem_update_rhs(h, _dptr(b), float(lam), _stream(stream)))
 
 
 def sca_problem_destroy(h):
@@ -348,6 +356,21 @@ def sca_batch_objective(h, opts, x_all, K, stream=None):
                 nnz=np.array(nnz[:]))
 
 
+def sca_batch_update_rhs(h, b_all, lam, stream=None):
+    a = np.ascontiguousarray(lam, dtype=np.float64)
+    _check(lib().sca_batch_update_rhs(h, _dptr(b_all), a.ctypes.data_as(ctypes.POINTER(_D)),
+                                      _stream(stream)))
+
+
+def sca_batch_adjoint(h, opts, xstar_all, xbar_all, bbar_all, K, cg_tol=0.0, cg_maxit=0,
+                      stream=None):
+    lb = (_D * K)()
+    _check(lib().sca_batch_adjoint(h, ctypes.byref(opts), _dptr(xstar_all), _dptr(xbar_all),
+                                   _dptr(bbar_all), lb, float(cg_tol), int(cg_maxit),
+                                   _stream(stream)))
+    return np.array(lb[:])
+
+
 class Batch:
     """Batch handle plus the per-instance device tensors it borrows."""
 
@@ -373,3 +396,48 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ autograd
+class SolveFn(torch.autograd.Function):
+    """x* = argmin of the problem for right-hand side b and weight lam (forward: sca_solve
+    from x = 0; backward: sca_adjoint).  ``problem`` is a Problem over the same A; its
+    right-hand side and lam are replaced by the inputs."""
+
+    @staticmethod
+    def forward(ctx, b, lam, problem, opts):
+        sca_problem_update_rhs(problem.handle, b, float(lam))
+        x = torch.zeros(problem.n, dtype=problem.dtype, device=b.device)
+        sca_solve(problem.handle, opts, x)
+        ctx.save_for_backward(x)
+        ctx.problem, ctx.opts = problem, opts
+        ctx.keep_b = b
+        return x
+
+    @staticmethod
+    def backward(ctx, xbar):
+        (x,) = ctx.saved_tensors
+        bbar = torch.empty(ctx.problem.m, dtype=ctx.problem.dtype, device=x.device)
+        lb = sca_adjoint(ctx.problem.handle, ctx.opts, x, xbar.contiguous(), bbar)
+        return bbar, torch.tensor(lb, dtype=torch.float64, device=x.device), None, None
+
+
+class BatchSolveFn(torch.autograd.Function):
+    """The batched form of SolveFn: b_all in the batch's r layout, lam one per instance."""
+
+    @staticmethod
+    def forward(ctx, b_all, lam, batch, opts):
+        sca_batch_update_rhs(batch.handle, b_all, lam.detach().double().cpu().numpy())
+        x = torch.zeros(int(batch.xoff[-1]), dtype=batch.dtype, device=b_all.device)
+        sca_batch_solve(batch.handle, opts, x, batch.K)
+        ctx.save_for_backward(x)
+        ctx.batch, ctx.opts = batch, opts
+        return x
+
+    @staticmethod
+    def backward(ctx, xbar):
+        (x,) = ctx.saved_tensors
+        bbar = torch.zeros(int(ctx.batch.roff[-1]), dtype=ctx.batch.dtype, device=x.device)
+        lb = sca_batch_adjoint(ctx.batch.handle, ctx.opts, x, xbar.contiguous(), bbar,
+                               ctx.batch.K)
+        return bbar, torch.as_tensor(lb, dtype=torch.float64, device=x.device), None, None
