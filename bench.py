@@ -77,6 +77,121 @@ def cpu_baseline(w, opts_kw, rounds):
                        f"({upd} coordinate updates in {dt:.1f} s, FP64 numpy)")
 
 
+def batch_reference_optima(ws, gamma, p, seed, budget_bytes=24e9):
+    """F*_k by FP64 batched solves (upcast copies, in chunks that fit beside the FP32 data)
+    to merit <= 1e-11 per instance."""
+    F = []
+    k0 = 0
+    while k0 < len(ws):
+        k1, nb = k0, 0.0
+        while k1 < len(ws) and (k1 == k0 or nb + ws[k1].At.numel() * 8 <= budget_bytes):
+            nb += ws[k1].At.numel() * 8
+            k1 += 1
+        chunk = []
+        for w in ws[k0:k1]:
+            chunk.append(inputs.DenseWorkload(w.name, w.At.double(), w.m, w.n, w.lda, w.b.double(),
+                                              w.x_true, w.lam, w.c, w.beta, w.tau, w.block_ptr,
+                                              w.p, w.gamma, w.seed, w.instance))
+        B = sca.Batch(chunk)
+        o = sca.make_opts(gamma=gamma, select_p=p, seed=seed, max_rounds=200000, check_every=50,
+                          tol_merit=1e-11)
+        x = torch.zeros(int(B.xoff[-1]), dtype=torch.float64, device="cuda")
+        st = sca.sca_batch_solve(B.handle, o, x, B.K, raise_on_notconv=False)
+        F += [s["F"] for s in st]
+        log(f"F* for instances {k0}..{k1 - 1}: max rounds {max(s['rounds'] for s in st)}, "
+            f"max merit {max(s['merit'] for s in st):.1e}")
+        B.close()
+        del chunk, x
+        torch.cuda.empty_cache()
+        k0 = k1
+    return F
+
+
+def bench_batch(args):
+    """256 LASSO instances, m_k uniform in [500, 8000], n_k = 5 m_k, FP32, lam_k log-spaced
+    over [1e-3, 1e-1] ||A_k^T b_k||_inf, 2% sparse x*, blocks of 64, p = 0.25, gamma 0.9:
+    batched solve to rel. error 1e-6 against the same instances solved one after another by
+    the plain path, then the batched adjoint against the plain adjoints."""
+    K = args.instances
+    t0 = time.perf_counter()
+    ws = inputs.batch_lasso(K, m_range=(500, 8000), nnz_frac=0.02, lam_range=(1e-3, 1e-1),
+                            block=64, p=0.25, dtype=torch.float32, seed=0, device="cuda")
+    torch.cuda.synchronize()
+    abytes = sum(w.At.numel() for w in ws) * 4
+    log(f"generated {K} instances ({abytes / 1e9:.1f} GB of A) in {time.perf_counter() - t0:.1f} s")
+    gamma, p, seed = 0.9, 0.25, 0
+    t0 = time.perf_counter()
+    F_star = batch_reference_optima(ws, gamma, p, seed)
+    log(f"F* for all instances in {time.perf_counter() - t0:.1f} s")
+    B = sca.Batch(ws, F_star)
+    o = sca.make_opts(gamma=gamma, select_p=p, seed=seed, max_rounds=100000, check_every=10,
+                      tol_rel_obj=args.tol)
+    x = torch.zeros(int(B.xoff[-1]), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        x.zero_()
+        sca.sca_batch_solve(B.handle, o, x, B.K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.zero_()
+        st = sca.sca_batch_solve(B.handle, o, x, B.K)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    upd_batch = sum(s["coord_updates"] for s in st)
+    log(f"batched solve: {t_batch * 1e3:.1f} ms, rounds max {max(s['rounds'] for s in st)}, "
+        f"max rel err {max(s['rel_err'] for s in st):.2e}")
+    # the same instances, one plain solve after another
+    plain_t, plain_upd, plain_x = 0.0, 0, []
+    probs = [sca.Problem.from_workload(w) for w in ws]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, (w, P) in enumerate(zip(ws, probs)):
+        ok = sca.make_opts(gamma=gamma, tau=w.tau, select_p=p, seed=seed, instance=k,
+                           max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
+                           F_star=F_star[k])
+        xk = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+        sk = sca.sca_solve(P.handle, ok, xk)
+        plain_upd += sk["coord_updates"]
+        plain_x.append(xk)
+    torch.cuda.synchronize()
+    plain_t = time.perf_counter() - t0
+    log(f"plain sequential solves: {plain_t * 1e3:.1f} ms")
+    # adjoints at the solutions, cotangent xbar = 1
+    xbar = torch.ones_like(x)
+    bbar = torch.zeros(int(B.roff[-1]), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb = sca.sca_batch_adjoint(B.handle, o, x, xbar, bbar, B.K)
+    torch.cuda.synchronize()
+    t_badj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k, (w, P) in enumerate(zip(ws, probs)):
+        ok = sca.make_opts(gamma=gamma, tau=w.tau, select_p=p, seed=seed, instance=k)
+        bb = torch.empty(w.m, dtype=torch.float32, device="cuda")
+        sca.sca_adjoint(P.handle, ok, plain_x[k], torch.ones_like(plain_x[k]), bb)
+    torch.cuda.synchronize()
+    t_padj = time.perf_counter() - t0
+    log(f"adjoints: batched {t_badj * 1e3:.1f} ms, plain sequential {t_padj * 1e3:.1f} ms")
+    out = {
+        "metric": METRIC, "value": upd_batch / t_batch, "unit": "coord-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch_{K}_lasso_m500-8000_n5m_fp32", "instances": K,
+                   "A_bytes": abytes, "block": 64, "select_p": p, "gamma": gamma,
+                   "tol_rel_obj": args.tol, "step": "one batched solve of every instance"},
+        "batched": {"time_to_all_tol_s": t_batch, "coord_updates_per_s": upd_batch / t_batch,
+                    "max_rel_err": max(s["rel_err"] for s in st)},
+        "plain_sequential": {"time_to_all_tol_s": plain_t,
+                             "coord_updates_per_s": plain_upd / plain_t},
+        "batched_speedup": plain_t / t_batch,
+        "adjoint": {"batched_s": t_badj, "plain_sequential_s": t_padj,
+                    "batched_over_forward": t_badj / t_batch,
+                    "lambar_first": float(lb[0])},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +203,8 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--workload", choices=["lasso", "batch"], default="lasso")
+    ap.add_argument("--instances", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (column-block sharding with "
@@ -98,6 +215,9 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     sca.lib()
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     t0 = time.perf_counter()
     w = inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")

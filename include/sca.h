@@ -242,8 +242,10 @@ sca_status sca_batch_step(sca_batch* batch, const sca_opts* opts, int64_t round_
                           int64_t nrounds, void* x_all_dev, void* r_all_dev, void* stream);
 
 /* Solve every instance from x_all (in: x^0, out: x).  Rounds run in graph launches of
- * check_every rounds followed by a fresh FP64 residual and, per instance, the test
- * (F - F_star)/|F_star| <= tol_rel_obj; a converged instance stops drawing blocks.  stats
+ * check_every rounds followed by a fresh FP64 residual and, per instance, the tests
+ * (F - F_star)/|F_star| <= tol_rel_obj and (when tol_merit > 0, at the cost of a full
+ * pass over every A) ||xh(x) - x||_inf <= tol_merit; a converged instance stops drawing
+ * blocks.  stats
  * (count entries, may be NULL) receive per-instance results.  Synchronises 'stream';
  * returns SCA_ENOTCONV when an instance ran out of max_rounds. */
 sca_status sca_batch_solve(sca_batch* batch, const sca_opts* opts, void* x_all_dev,

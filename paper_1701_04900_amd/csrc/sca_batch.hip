@@ -476,6 +476,18 @@ k_bprobe_reduce(int K, const BInst* __restrict__ inst, const double* __restrict_
   }
 }
 
+// Per-instance merit test after a probe: deactivate instances with merit <= tol.
+__global__ void k_bmerit_check(int K, const double* __restrict__ pr, double tol,
+                               const BState* __restrict__ st, int* __restrict__ active,
+                               long long* __restrict__ done_round) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    if (active[k] && pr[3 * k] <= tol) {
+      active[k] = 0;
+      done_round[k] = st->rs.k;
+    }
+  }
+}
+
 __global__ void k_binit(BState* st, long long k, double gamma, double mu, int Ntot, int K,
                         int* active, long long* done_round, long long* inst_upd, int reset) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < K; q += gridDim.x * blockDim.x) {
@@ -946,12 +958,19 @@ extern "C" sca_status sca_batch_objective(sca_batch* B, const sca_opts* o, const
   return SCA_OK;
 }
 
-// E rounds followed by a fresh FP64 residual and the per-instance stopping test.
+// E rounds followed by a fresh FP64 residual and the per-instance stopping tests
+// (relative objective error, and the merit when tol_merit > 0).
 template <typename T>
 static void batch_cycle(sca_batch* B, const sca_opts* o, T* x, T* r, hipStream_t s) {
   for (int64_t i = 0; i < o->check_every; ++i) batch_round<T>(B, o, x, r, s);
   batch_residual<T>(B, x, r, s);
   batch_check<T>(B, x, o->tol_rel_obj, s);
+  if (o->tol_merit > 0.0) {
+    batch_probe<T>(B, x, s);
+    hipLaunchKernelGGL(k_bmerit_check, dim3(std::max(1, (B->K + 255) / 256)), dim3(256), 0, s,
+                       B->K, (const double*)B->d_pr, o->tol_merit, (const BState*)B->d_state,
+                       B->d_active, B->d_done);
+  }
 }
 
 extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
@@ -979,7 +998,8 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
     batch_residual<double>(B, (const double*)x, (double*)r, s);
   // one graph = check_every rounds + check; built once per (x, check_every, tol)
   if (!B->graph || B->graph_rounds != o->check_every || B->graph_x != x ||
-      B->graph_tol != o->tol_rel_obj) {
+      B->graph_tol != o->tol_rel_obj || B->graph_tol_merit != o->tol_merit ||
+      B->graph_p != o->select_p || B->graph_seed != o->seed) {
     if (B->graph) {
       (void)hipGraphExecDestroy(B->graph);
       B->graph = nullptr;
@@ -1002,6 +1022,9 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
     B->graph_rounds = (int)o->check_every;
     B->graph_x = x;
     B->graph_tol = o->tol_rel_obj;
+    B->graph_tol_merit = o->tol_merit;
+    B->graph_p = o->select_p;
+    B->graph_seed = o->seed;
   }
   std::vector<int> act(B->K);
   int64_t k = 0;
@@ -1036,7 +1059,8 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
   for (int q = 0; q < B->K; ++q) {
     const bool conv = done[q] >= 0;
     const bool fin = std::isfinite(F[q]);
-    if (!conv && o->tol_rel_obj > 0.0) ++notconv;
+    const bool want = o->tol_rel_obj > 0.0 || o->tol_merit > 0.0;
+    if (!conv && want) ++notconv;
     if (stats) {
       sca_stats& S = stats[q];
       S.rounds = conv ? done[q] : k;
@@ -1049,7 +1073,7 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
       S.rel_err = fs != 0.0 ? (F[q] - fs) / std::fabs(fs) : 0.0;
       S.seconds = secs;
       S.nnz = nnz[q];
-      S.status = !fin ? SCA_ENONFINITE : ((!conv && o->tol_rel_obj > 0.0) ? SCA_ENOTCONV : SCA_OK);
+      S.status = !fin ? SCA_ENONFINITE : ((!conv && want) ? SCA_ENOTCONV : SCA_OK);
       S.checks = checks;
     }
   }

@@ -86,5 +86,8 @@ struct sca_batch {
   int graph_rounds = 0;
   const void* graph_x = nullptr;
   double graph_tol = 0;
+  double graph_tol_merit = 0;
+  double graph_p = 0;
+  uint64_t graph_seed = 0;
 };
 
