@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--m", type=int, default=20000)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-rounds", type=int, default=3)
+    ap.add_argument("--cpu-rounds", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", choices=["lasso", "batch"], default="lasso")
@@ -231,15 +231,14 @@ def main():
         f"{time.perf_counter() - t0:.1f} s)")
 
     P = sca.Problem.from_workload(w)
-    flags = 0 if args.no_profile else sca.SCA_FLAG_PROFILE
     opts = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
-                         F_star=F_star, flags=flags)
+                         F_star=F_star)
     x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
     for i in range(args.warmup):
         x.zero_()
         st = sca.sca_solve(P.handle, opts, x)
         log(f"warmup solve {i}: {st['rounds']} rounds, rel err {st['rel_err']:.2e}")
-    sca.sca_profile_get(P.handle, reset=True)
+    # timed region: K solves, each check cycle one graph launch
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
@@ -248,7 +247,6 @@ def main():
         stats.append(sca.sca_solve(P.handle, opts, x))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    prof = sca.sca_profile_get(P.handle, reset=True)
     updates = sum(s["coord_updates"] for s in stats)
     rounds = sum(s["rounds"] for s in stats)
     value = updates / elapsed
@@ -256,18 +254,55 @@ def main():
         log(f"solve {i}: {s['rounds']} rounds, {s['coord_updates']} updates, "
             f"{s['seconds'] * 1e3:.1f} ms, rel err {s['rel_err']:.3e}, merit {s['merit']:.2e}")
 
-    roof = None
-    if not args.no_profile and prof["grad"]["launches"]:
+    roof, prof_pass = None, None
+    if not args.no_profile:
+        # the same K solves again with HIP events around every kernel launch (eager launches
+        # on the caller's stream: events cannot time kernels inside a replayed graph)
+        popts = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10,
+                              tol_rel_obj=args.tol, F_star=F_star, flags=sca.SCA_FLAG_PROFILE)
+        sca.sca_profile_get(P.handle, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pst = []
+        for i in range(args.steps):
+            x.zero_()
+            pst.append(sca.sca_solve(P.handle, popts, x))
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        prof = sca.sca_profile_get(P.handle, reset=True)
+        pupd = sum(s["coord_updates"] for s in pst)
+        pmoved = sum(s["moved_updates"] for s in pst)
         g = prof["grad"]
-        bytes_total = float(updates) * w.m * w.At.element_size()
+        bytes_total = float(pupd) * w.m * w.At.element_size()
         avg_ms = g["ms"] / g["launches"]
         achieved = bytes_total / (g["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel="k_grad_br<float,8>", avg_launch_ms=round(avg_ms, 4),
+                    kernel="k_grad_br_wg<float,8,2>", avg_launch_ms=round(avg_ms, 4),
                     alg_bytes_per_launch=round(bytes_total / g["launches"]))
-        other = {k: round(v["ms"] / max(1, v["launches"]), 4) for k, v in prof.items()}
-        log(f"per-launch ms by kernel kind: {other}")
+        # achievable read bandwidth on the same 8 GB matrix: a plain 16-byte streaming read
+        sink = torch.zeros(1 << 14, dtype=torch.float32, device="cuda")
+        nbytes = w.At.numel() * w.At.element_size() // 16 * 16
+        best = 0.0
+        for grid in (1024, 2048):
+            sca.sca_stream_read(w.At, nbytes, sink, grid)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                sca.sca_stream_read(w.At, nbytes, sink, grid)
+            e1.record()
+            torch.cuda.synchronize()
+            best = max(best, 3 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        roof["read_stream_peak"] = round(best, 1)
+        roof["frac_of_read_stream_peak"] = round(achieved / best, 4)
+        fold_b = float(pmoved) * w.m * w.At.element_size()
+        f = prof["fold"]
+        prof_pass = dict(ms_per_step=pel / args.steps * 1e3,
+                         per_launch_ms={k: round(v["ms"] / max(1, v["launches"]), 4)
+                                        for k, v in prof.items()},
+                         fold_GBps=round(fold_b / (f["ms"] * 1e-3) / 1e9, 1) if f["ms"] else None,
+                         moved_per_round=pmoved / max(1, sum(s["rounds"] for s in pst)))
+        log(f"profiled pass: {prof_pass}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -296,6 +331,7 @@ def main():
         "rel_err_final": [s["rel_err"] for s in stats],
         "F_star": F_star,
         "roofline": roof,
+        "profiled_pass": prof_pass,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

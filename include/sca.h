@@ -190,6 +190,16 @@ sca_status sca_adjoint(sca_problem* p, const sca_opts* opts, const void* xstar_d
 sca_status sca_profile_get(sca_problem* p, double* ms_host, int64_t* launches_host,
                            double* bytes_host, int reset);
 
+/* Measurement utilities (not part of the method): a streaming copy of 'bytes' from src to
+ * dst and a streaming read of src, 16-byte accesses over 'grid' workgroups of 256 threads
+ * (grid <= 0: four per compute unit).  sink_dev receives at most 'grid' floats and is
+ * practically never written.  Buffers 16-byte aligned, bytes a multiple of 16.
+ * Stream-ordered.  They give the achievable bandwidth and calibrate byte counters. */
+sca_status sca_stream_copy(void* dst_dev, const void* src_dev, int64_t bytes, int32_t grid,
+                           void* stream);
+sca_status sca_stream_read(const void* src_dev, int64_t bytes, void* sink_dev, int32_t grid,
+                           void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Batched form: many dense instances of uneven size advance together, one round of every
  * active instance per launch sequence (a block-diagonal problem).  Instance k follows the

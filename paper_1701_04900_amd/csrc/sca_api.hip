@@ -98,10 +98,13 @@ void sca::apply_launch_env(sca_problem* p) {
     const int u = atoi(e);
     if (u == 1 || u == 2 || u == 4 || u == 8 || u == 16) p->grad_unroll = u;
   }
-  if (const char* e = getenv("SCA_GRAD_KIND")) p->grad_kind = atoi(e) == 1 ? 1 : 0;
+  if (const char* e = getenv("SCA_GRAD_KIND")) {
+    const int k = atoi(e);
+    if (k >= 0 && k <= 2) p->grad_kind = k;
+  }
   if (const char* e = getenv("SCA_GRAD_COLS")) {
     const int c = atoi(e);
-    if (c == 2 || c == 4 || c == 8) p->grad_cols = c;
+    if (c == 2 || c == 4 || c == 8 || c == 16) p->grad_cols = c;
   }
   if (const char* e = getenv("SCA_GRAD_WG_PER_CU")) {
     const int w = atoi(e);
@@ -184,6 +187,10 @@ void sca::free_workspace(sca_problem* p) {
     if (q) (void)hipFree(q);
   adjoint_release(p->adj);
   p->adj = nullptr;
+  if (p->sgraph) (void)hipGraphExecDestroy(p->sgraph);
+  p->sgraph = nullptr;
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  p->cap = nullptr;
   for (auto& e : p->events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -278,7 +285,7 @@ extern "C" sca_status sca_problem_set_regularizer(sca_problem* p, sca_reg reg, d
   if (reg != SCA_REG_EXP && reg != SCA_REG_LOG) return set_error(SCA_EINVAL, "unknown regulariser");
   if (!(theta > 0.0) || !std::isfinite(theta)) return set_error(SCA_EINVAL, "theta must be > 0");
   p->reg = (int)reg;
-  p->theta = theta;
+  p->theta = theta;  // (the solve graph compares its baked-in parameters before reuse)
   p->eta = reg == SCA_REG_EXP ? theta : theta / std::log1p(theta);
   return SCA_OK;
 }
@@ -383,11 +390,25 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
   hipLaunchKernelGGL((k_grad_br<T, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,           \
                      (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,         \
                      p->d_state, (T*)p->d_dx_sel, bp)
+#define GRAD_WG_LAUNCH_NT(CC, UU, NTT)                                                      \
+  hipLaunchKernelGGL((k_grad_br_wg<T, CC, UU, NTT>), ggrid, dim3(256), 0, s, (const T*)p->A, \
+                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
+                     p->d_state, (T*)p->d_dx_sel, bp)
 #define GRAD_WG_LAUNCH(CC, UU)                                                              \
   hipLaunchKernelGGL((k_grad_br_wg<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,      \
                      (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
                      p->d_state, (T*)p->d_dx_sel, bp)
-  if (p->grad_kind == 1) {
+  if (p->grad_kind == 2) {  // ordinary (temporal) loads
+    if (p->grad_cols == 16)
+      GRAD_WG_LAUNCH_NT(16, 1, false);
+    else
+      GRAD_WG_LAUNCH_NT(8, 2, false);
+  } else if (p->grad_kind == 1 && p->grad_cols == 16) {
+    if (p->grad_unroll == 2)
+      GRAD_WG_LAUNCH_NT(16, 2, true);
+    else
+      GRAD_WG_LAUNCH_NT(16, 1, true);
+  } else if (p->grad_kind == 1) {
     if (p->grad_cols == 2 && p->grad_unroll == 4)
       GRAD_WG_LAUNCH(2, 4);
     else if (p->grad_cols == 4 && p->grad_unroll == 4)
@@ -409,6 +430,7 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
   }
 #undef GRAD_LAUNCH
 #undef GRAD_WG_LAUNCH
+#undef GRAD_WG_LAUNCH_NT
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_COMPACT);
   const int nch = (n + kChunk - 1) / kChunk;
@@ -626,6 +648,42 @@ extern "C" sca_status sca_objective(sca_problem* p, const sca_opts* o, const voi
   return report(p, o, x, F, merit, MF, nnz, (hipStream_t)stream);
 }
 
+// One graph = check_every rounds followed by the FP64 objective of the running residual
+// (into d_scal[0]); rebuilt when any baked-in argument changes.
+static sca_status solve_graph(sca_problem* p, const sca_opts* o, void* x, void* r,
+                              const BRParams& bp) {
+  const double key[12] = {(double)(uintptr_t)x, (double)(uintptr_t)r, (double)o->check_every,
+                          o->select_p, (double)o->seed, (double)o->instance, o->tau, p->lam,
+                          p->c, p->beta, (double)p->reg, p->theta};
+  bool same = p->sgraph != nullptr;
+  for (int i = 0; same && i < 12; ++i) same = key[i] == p->skey[i] || (key[i] != key[i] && p->skey[i] != p->skey[i]);
+  if (same) return SCA_OK;
+  if (p->sgraph) {
+    (void)hipGraphExecDestroy(p->sgraph);
+    p->sgraph = nullptr;
+  }
+  if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+    return set_error(SCA_EHIP, "stream creation failed");
+  hipGraph_t g;
+  if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return set_error(SCA_EHIP, "graph capture failed to start");
+  if (p->dtype == SCA_F32)
+    run_rounds_t<float>(p, o, o->check_every, (float*)x, (float*)r, p->cap);
+  else
+    run_rounds_t<double>(p, o, o->check_every, (double*)x, (double*)r, p->cap);
+  objective_any(p, x, r, false, bp, p->d_scal, p->cap);
+  if (hipStreamEndCapture(p->cap, &g) != hipSuccess)
+    return set_error(SCA_EHIP, "graph capture failed");
+  const hipError_t e = hipGraphInstantiate(&p->sgraph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    p->sgraph = nullptr;
+    return set_error(SCA_EHIP, "graph instantiation failed");
+  }
+  for (int i = 0; i < 12; ++i) p->skey[i] = key[i];
+  return SCA_OK;
+}
+
 extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_stats* stats,
                                 void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -651,16 +709,25 @@ extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_
   int32_t checks = 0;
   sca_status result = SCA_ENOTCONV;
   double F = NAN;
+  // without profiling, whole checks run as one graph launch (rounds + objective)
+  const bool use_graph = !p->profiling;
+  if (use_graph && (st = solve_graph(p, o, x, r, bp)) != SCA_OK) return st;
   while (k < o->max_rounds) {
     const int64_t nr = std::min<int64_t>(o->check_every, o->max_rounds - k);
-    if (p->dtype == SCA_F32)
-      run_rounds_t<float>(p, o, nr, (float*)x, (float*)r, s);
-    else
-      run_rounds_t<double>(p, o, nr, (double*)x, (double*)r, s);
+    const bool refresh = o->refresh_every > 0 && (checks + 1) % o->refresh_every == 0;
+    if (use_graph && nr == o->check_every && !refresh) {
+      if (hipGraphLaunch(p->sgraph, s) != hipSuccess)
+        return set_error(SCA_EHIP, "graph launch failed");
+    } else {
+      if (p->dtype == SCA_F32)
+        run_rounds_t<float>(p, o, nr, (float*)x, (float*)r, s);
+      else
+        run_rounds_t<double>(p, o, nr, (double*)x, (double*)r, s);
+      if (refresh) residual_any(p, x, r, s);
+      objective_any(p, x, r, false, bp, p->d_scal, s);
+    }
     k += nr;
     ++checks;
-    if (o->refresh_every > 0 && checks % o->refresh_every == 0) residual_any(p, x, r, s);
-    objective_any(p, x, r, false, bp, p->d_scal, s);
     if (hipMemcpyAsync(&F, p->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return set_error(SCA_EHIP, "solve: %s", hipGetErrorString(hipGetLastError()));

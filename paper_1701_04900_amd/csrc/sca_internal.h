@@ -61,6 +61,11 @@ struct sca_problem {
 
   sca_adj_cache* adj = nullptr;
 
+  // graph of check_every rounds + objective used by sca_solve (built on first use)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t sgraph = nullptr;
+  double skey[12] = {0};
+
   // profiling
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

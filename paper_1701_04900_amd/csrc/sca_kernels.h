@@ -272,7 +272,7 @@ k_grad_br(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r
 // columns; U row steps are kept in flight.  Groups of C consecutive drawn coordinates are
 // handed out by an integer counter.  The per-thread partial dots are reduced in a fixed
 // order (wave butterfly, then the four waves in order) before the best response.
-template <typename T, int C, int U>
+template <typename T, int C, int U, bool NT = true>
 __global__ void __launch_bounds__(256)
 k_grad_br_wg(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
              T* __restrict__ x, const double* __restrict__ cn2, const int* __restrict__ sel_cols,
@@ -313,7 +313,8 @@ k_grad_br_wg(const T* __restrict__ A, long long lda, int m, const T* __restrict_
         rv[u] = *reinterpret_cast<const VA*>(r + row);
 #pragma unroll
         for (int c = 0; c < C; ++c)
-          a[u][c] = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row));
+          a[u][c] = NT ? __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row))
+                       : *reinterpret_cast<const VA*>(col[c] + row);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -327,7 +328,8 @@ k_grad_br_wg(const T* __restrict__ A, long long lda, int m, const T* __restrict_
       const VA rv = *reinterpret_cast<const VA*>(r + row);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const VA a = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row));
+        const VA a = NT ? __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row))
+                        : *reinterpret_cast<const VA*>(col[c] + row);
 #pragma unroll
         for (int e = 0; e < VN; ++e) acc[c] += a[e] * rv[e];
       }

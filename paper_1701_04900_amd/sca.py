@@ -88,6 +88,8 @@ SIGNATURES = {
                          _P]),
     "sca_profile_get": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D),
                              _S]),
+    "sca_stream_copy": (_S, [_P, _P, _I64, ctypes.c_int32, _P]),
+    "sca_stream_read": (_S, [_P, _I64, _P, ctypes.c_int32, _P]),
     "sca_batch_create": (_S, [ctypes.POINTER(_P), _S, _I64, ctypes.POINTER(sca_batch_item), _P]),
     "sca_batch_destroy": (None, [_P]),
     "sca_batch_layout": (_S, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -243,6 +245,14 @@ def sca_profile_get(h, reset=False):
     _check(lib().sca_profile_get(h, ms, n, by, int(reset)))
     names = ["select", "grad", "compact", "fold"]
     return {names[k]: dict(ms=ms[k], launches=n[k], bytes=by[k]) for k in range(SCA_K_NKINDS)}
+
+
+def sca_stream_copy(dst, src, nbytes, grid=0, stream=None):
+    _check(lib().sca_stream_copy(_dptr(dst), _dptr(src), int(nbytes), int(grid), _stream(stream)))
+
+
+def sca_stream_read(src, nbytes, sink, grid=0, stream=None):
+    _check(lib().sca_stream_read(_dptr(src), int(nbytes), _dptr(sink), int(grid), _stream(stream)))
 
 
 # ------------------------------------------------------------------ convenience holder
