@@ -276,9 +276,14 @@ def main():
         bytes_total = float(pupd) * w.m * w.At.element_size()
         avg_ms = g["ms"] / g["launches"]
         achieved = bytes_total / (g["ms"] * 1e-3) / 1e9
+        L = sca.sca_problem_get_launch(P.handle)
+        kname = {0: f"k_grad_br<float,{L['grad_unroll']}>",
+                 1: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},true>",
+                 2: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},false>",
+                 3: f"k_grad_br_wwalk<float,{L['grad_cols']},{L['grad_unroll']}>"}[L["grad_kind"]]
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    kernel="k_grad_br_wg<float,8,2>", avg_launch_ms=round(avg_ms, 4),
+                    kernel=kname, launch=L, avg_launch_ms=round(avg_ms, 4),
                     alg_bytes_per_launch=round(bytes_total / g["launches"]))
         # achievable read bandwidth on the same 8 GB matrix: a plain 16-byte streaming read
         sink = torch.zeros(1 << 14, dtype=torch.float32, device="cuda")

@@ -190,6 +190,39 @@ sca_status sca_adjoint(sca_problem* p, const sca_opts* opts, const void* xstar_d
 sca_status sca_profile_get(sca_problem* p, double* ms_host, int64_t* launches_host,
                            double* bytes_host, int reset);
 
+/* Launch shape of the gradient kernel (the dominant kernel).
+ *  grad_kind 0: one wave per drawn column, grad_unroll in {4, 8, 16} 16-byte loads in flight;
+ *  grad_kind 1: one 256-thread workgroup walks grad_cols columns together with grad_unroll
+ *    row steps in flight, (cols, unroll) in {(2,4), (4,1), (4,2), (4,4), (8,1), (8,2), (16,1),
+ *    (16,2)}, non-temporal loads;
+ *  grad_kind 2: as 1 with ordinary loads, (cols, unroll) in {(8,2), (16,1)};
+ *  grad_kind 3: every wave walks its own group of grad_cols columns (short columns),
+ *    (cols, unroll) in {(4,2), (4,4), (8,1)};
+ *  grad_wg_per_cu in [1, 16]: persistent workgroups per compute unit. */
+typedef struct {
+  size_t struct_size; /* = sizeof(sca_launch) */
+  int32_t grad_kind;
+  int32_t grad_cols;
+  int32_t grad_unroll;
+  int32_t grad_wg_per_cu;
+} sca_launch;
+
+/* One row of the tuning table: problems of this dtype with m_lo <= m <= m_hi get 'launch'. */
+typedef struct {
+  int32_t dtype; /* sca_dtype */
+  int32_t reserved;
+  int64_t m_lo, m_hi;
+  sca_launch launch;
+} sca_tune_entry;
+
+/* Replace the process-wide tuning table (count rows, copied; count 0 clears it).  Problems
+ * created afterwards take the first matching row, else the built-in default. */
+sca_status sca_tuning_set(const sca_tune_entry* entries_host, int64_t count);
+
+/* Read / override the launch shape of one problem.  Rejects shapes outside the lists above. */
+sca_status sca_problem_get_launch(sca_problem* p, sca_launch* out);
+sca_status sca_problem_set_launch(sca_problem* p, const sca_launch* launch);
+
 /* Measurement utilities (not part of the method): a streaming copy of 'bytes' from src to
  * dst and a streaming read of src, 16-byte accesses over 'grid' workgroups of 256 threads
  * (grid <= 0: four per compute unit).  sink_dev receives at most 'grid' floats and is

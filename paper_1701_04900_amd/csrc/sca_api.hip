@@ -91,25 +91,72 @@ BRParams sca::make_brparams(const sca_problem* p, double tau) {
   return bp;
 }
 
-// Launch-shape overrides (used by the tuning sweeps): SCA_GRAD_UNROLL in {4, 8, 16},
-// SCA_GRAD_WG_PER_CU in [1, 16].
-void sca::apply_launch_env(sca_problem* p) {
-  if (const char* e = getenv("SCA_GRAD_UNROLL")) {
-    const int u = atoi(e);
-    if (u == 1 || u == 2 || u == 4 || u == 8 || u == 16) p->grad_unroll = u;
+// ------------------------------------------------------------------ launch shapes
+static bool launch_valid(const sca_launch* l) {
+  if (!l || l->struct_size != sizeof(sca_launch)) return false;
+  if (l->grad_wg_per_cu < 1 || l->grad_wg_per_cu > 16) return false;
+  const int c = l->grad_cols, u = l->grad_unroll;
+  switch (l->grad_kind) {
+    case 0:
+      return u == 4 || u == 8 || u == 16;
+    case 1:
+      return (c == 2 && u == 4) || (c == 4 && (u == 1 || u == 2 || u == 4)) ||
+             (c == 8 && (u == 1 || u == 2)) || (c == 16 && (u == 1 || u == 2));
+    case 2:
+      return (c == 8 && u == 2) || (c == 16 && u == 1);
+    case 3:
+      return (c == 4 && (u == 2 || u == 4)) || (c == 8 && u == 1);
+    default:
+      return false;
   }
-  if (const char* e = getenv("SCA_GRAD_KIND")) {
-    const int k = atoi(e);
-    if (k >= 0 && k <= 2) p->grad_kind = k;
+}
+
+static std::vector<sca_tune_entry> g_tuning;
+
+extern "C" sca_status sca_tuning_set(const sca_tune_entry* e, int64_t count) {
+  if (count < 0 || (count > 0 && !e)) return set_error(SCA_EINVAL, "bad tuning table");
+  for (int64_t i = 0; i < count; ++i)
+    if (!launch_valid(&e[i].launch) || e[i].m_lo > e[i].m_hi ||
+        (e[i].dtype != SCA_F32 && e[i].dtype != SCA_F64))
+      return set_error(SCA_EINVAL, "tuning row %lld is invalid", (long long)i);
+  g_tuning.assign(e, e + count);
+  return SCA_OK;
+}
+
+void sca::apply_tuning(sca_problem* p) {
+  for (const sca_tune_entry& e : g_tuning) {
+    if (e.dtype == p->dtype && p->m >= e.m_lo && p->m <= e.m_hi) {
+      p->grad_kind = e.launch.grad_kind;
+      p->grad_cols = e.launch.grad_cols;
+      p->grad_unroll = e.launch.grad_unroll;
+      p->grad_wg_per_cu = e.launch.grad_wg_per_cu;
+      return;
+    }
   }
-  if (const char* e = getenv("SCA_GRAD_COLS")) {
-    const int c = atoi(e);
-    if (c == 2 || c == 4 || c == 8 || c == 16) p->grad_cols = c;
+}
+
+extern "C" sca_status sca_problem_get_launch(sca_problem* p, sca_launch* out) {
+  if (!p || !out) return set_error(SCA_EINVAL, "NULL argument");
+  out->struct_size = sizeof(sca_launch);
+  out->grad_kind = p->grad_kind;
+  out->grad_cols = p->grad_cols;
+  out->grad_unroll = p->grad_unroll;
+  out->grad_wg_per_cu = p->grad_wg_per_cu;
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_problem_set_launch(sca_problem* p, const sca_launch* l) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  if (!launch_valid(l)) return set_error(SCA_EINVAL, "launch shape not available");
+  p->grad_kind = l->grad_kind;
+  p->grad_cols = l->grad_cols;
+  p->grad_unroll = l->grad_unroll;
+  p->grad_wg_per_cu = l->grad_wg_per_cu;
+  if (p->sgraph) {  // the solve graph bakes the launch shape in
+    (void)hipGraphExecDestroy(p->sgraph);
+    p->sgraph = nullptr;
   }
-  if (const char* e = getenv("SCA_GRAD_WG_PER_CU")) {
-    const int w = atoi(e);
-    if (w >= 1 && w <= 16) p->grad_wg_per_cu = w;
-  }
+  return SCA_OK;
 }
 
 // ------------------------------------------------------------------ problem lifetime
@@ -263,7 +310,7 @@ extern "C" sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtyp
   p->beta = beta;
   p->nblocks = nblocks;
   p->ncu = device_cu_count();
-  apply_launch_env(p);
+  apply_tuning(p);
   if ((st = alloc_workspace(p, block_ptr)) != SCA_OK ||
       (st = finish_create(p, (hipStream_t)stream)) != SCA_OK) {
     free_workspace(p);
@@ -398,7 +445,18 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
   hipLaunchKernelGGL((k_grad_br_wg<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,      \
                      (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
                      p->d_state, (T*)p->d_dx_sel, bp)
-  if (p->grad_kind == 2) {  // ordinary (temporal) loads
+#define GRAD_WW_LAUNCH(CC, UU)                                                              \
+  hipLaunchKernelGGL((k_grad_br_wwalk<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,   \
+                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
+                     p->d_state, (T*)p->d_dx_sel, bp)
+  if (p->grad_kind == 3) {  // one wave per group of columns
+    if (p->grad_cols == 4 && p->grad_unroll == 2)
+      GRAD_WW_LAUNCH(4, 2);
+    else if (p->grad_cols == 8 && p->grad_unroll == 1)
+      GRAD_WW_LAUNCH(8, 1);
+    else
+      GRAD_WW_LAUNCH(4, 4);
+  } else if (p->grad_kind == 2) {  // ordinary (temporal) loads
     if (p->grad_cols == 16)
       GRAD_WG_LAUNCH_NT(16, 1, false);
     else
@@ -431,6 +489,7 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
 #undef GRAD_LAUNCH
 #undef GRAD_WG_LAUNCH
 #undef GRAD_WG_LAUNCH_NT
+#undef GRAD_WW_LAUNCH
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_COMPACT);
   const int nch = (n + kChunk - 1) / kChunk;

@@ -151,11 +151,19 @@ k_bgrad(const BInst* __restrict__ inst, const BItem* __restrict__ items,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nitems = st->items;
   const T gamma = (T)st->rs.gamma_cur;
+  const int GR = max(1, nitems / (int)(8 * gridDim.x));  // items taken per counter update
+  int item = 0, left = 0;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&st->rs.work_ctr, 1);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
+    if (left == 0) {
+      if (threadIdx.x == 0) s_item = atomicAdd(&st->rs.work_ctr, GR);
+      __syncthreads();
+      item = s_item;
+      left = GR;
+      __syncthreads();
+    } else {
+      ++item;
+    }
+    --left;
     if (item >= nitems) break;
     const BItem it = items[item];
     const BInst& I = inst[it.inst];

@@ -95,7 +95,7 @@ double gamma_at_round(double g0, double mu, long long k);
 uint64_t selection_threshold(double p);
 void prof_begin(sca_problem* p, hipStream_t s, int kind);
 void prof_end(sca_problem* p, hipStream_t s, double bytes);
-void apply_launch_env(sca_problem* p);
+void apply_tuning(sca_problem* p);
 void init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begin, hipStream_t s);
 void residual_any(sca_problem* p, const void* x, void* r_out, hipStream_t s);
 

@@ -287,19 +287,111 @@ k_grad_br_wg(const T* __restrict__ A, long long lda, int m, const T* __restrict_
   const int ngroups = (S + C - 1) / C;
   const T gamma = (T)st->gamma_cur;
   const int nfull = m / ROWS;  // steps where every thread holds VN valid rows
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&st->work_ctr, 1);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= ngroups) break;
+  // Few large items: an integer counter hands them out one at a time.
+  if (ngroups < 8 * (int)gridDim.x) {
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(&st->work_ctr, 1);
+      __syncthreads();
+      const int item = s_item;
+      __syncthreads();
+      if (item >= ngroups) break;
+      const int t0 = item * C;
+      const T* col[C];
+  #pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int t = min(t0 + c, S - 1);  // a short last group repeats its last column
+        col[c] = A + (size_t)sel_cols[t] * lda;
+      }
+      T acc[C];
+  #pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = (T)0;
+      const int row_t = threadIdx.x * VN;
+      int step = 0;
+      for (; step + U <= nfull; step += U) {
+        VA a[U][C], rv[U];
+  #pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = (step + u) * ROWS + row_t;
+          rv[u] = *reinterpret_cast<const VA*>(r + row);
+  #pragma unroll
+          for (int c = 0; c < C; ++c)
+            a[u][c] = NT ? __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row))
+                         : *reinterpret_cast<const VA*>(col[c] + row);
+        }
+  #pragma unroll
+        for (int u = 0; u < U; ++u)
+  #pragma unroll
+          for (int c = 0; c < C; ++c)
+  #pragma unroll
+            for (int e = 0; e < VN; ++e) acc[c] += a[u][c][e] * rv[u][e];
+      }
+      for (; step < nfull; ++step) {
+        const int row = step * ROWS + row_t;
+        const VA rv = *reinterpret_cast<const VA*>(r + row);
+  #pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const VA a = NT ? __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row))
+                          : *reinterpret_cast<const VA*>(col[c] + row);
+  #pragma unroll
+          for (int e = 0; e < VN; ++e) acc[c] += a[e] * rv[e];
+        }
+      }
+      {  // ragged tail: rows nfull*ROWS .. m-1
+        const int row = nfull * ROWS + row_t;
+        for (int e = 0; e < VN; ++e) {
+          if (row + e < m) {
+            const T rr = r[row + e];
+  #pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += col[c][row + e] * rr;
+          }
+        }
+      }
+  #pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const T v = wave_sum(acc[c]);
+        if (lane == 0) red[wave][c] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < C && t0 + (int)threadIdx.x < S) {
+        const int c = threadIdx.x;
+        const int t = t0 + c;
+        const int j = sel_cols[t];
+        const T dot = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        const T xj = x[j];
+        T g = dot - (T)bp.c2 * xj;
+        if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+        const T q = (T)(cn2[j] + bp.tau);
+        const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
+        const T d = gamma * (xh - xj);
+        x[j] = xj + d;
+        dx_sel[t] = d;
+      }
+    }
+    return;
+  }
+  // Many small items (short columns): fixed round-robin assignment, the next item's column
+  // indices and this item's best-response operands are loaded while the columns stream.
+  int item = blockIdx.x;
+  int jn[C];  // column indices of the item about to be processed
+  if (item < ngroups) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) jn[c] = sel_cols[min(item * C + c, S - 1)];
+  }
+  while (item < ngroups) {
     const int t0 = item * C;
     const T* col[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int t = min(t0 + c, S - 1);  // a short last group repeats its last column
-      col[c] = A + (size_t)sel_cols[t] * lda;
+    for (int c = 0; c < C; ++c) col[c] = A + (size_t)jn[c] * lda;
+    // best-response operands of this item (only threads c < C use them)
+    T xj = (T)0;
+    double qd = 0.0;
+    int jme = 0;
+    if ((int)threadIdx.x < C && t0 + (int)threadIdx.x < S) {
+      jme = jn[threadIdx.x];
+      xj = x[jme];
+      qd = cn2[jme];
     }
+    const int next = item + gridDim.x;
     T acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = (T)0;
@@ -350,13 +442,115 @@ k_grad_br_wg(const T* __restrict__ A, long long lda, int m, const T* __restrict_
       if (lane == 0) red[wave][c] = v;
     }
     __syncthreads();
-    if (threadIdx.x < C && t0 + (int)threadIdx.x < S) {
+    if ((int)threadIdx.x < C && t0 + (int)threadIdx.x < S) {
       const int c = threadIdx.x;
       const int t = t0 + c;
-      const int j = sel_cols[t];
       const T dot = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-      const T xj = x[j];
       T g = dot - (T)bp.c2 * xj;
+      if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+      const T q = (T)(qd + bp.tau);
+      const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
+      const T d = gamma * (xh - xj);
+      x[jme] = xj + d;
+      dx_sel[t] = d;
+    }
+    __syncthreads();  // red is reused by the next item
+    item = next;
+    if (item < ngroups) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) jn[c] = sel_cols[min(item * C + c, S - 1)];
+    }
+  }
+}
+
+// Wave variant of the walk for short columns: every wave takes its own group of C
+// consecutive drawn coordinates (integer work counter) and walks down them with 64 lanes x
+// 16-byte loads, U row steps in flight; a butterfly per column, then lanes 0..C-1 apply
+// the best response.
+template <typename T, int C, int U>
+__global__ void __launch_bounds__(256)
+k_grad_br_wwalk(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
+                T* __restrict__ x, const double* __restrict__ cn2,
+                const int* __restrict__ sel_cols, RoundState* __restrict__ st,
+                T* __restrict__ dx_sel, BRParams bp) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  constexpr int ROWS = 64 * VN;
+  const int lane = threadIdx.x & 63;
+  const int S = st->S_cnt;
+  const int ngroups = (S + C - 1) / C;
+  const T gamma = (T)st->gamma_cur;
+  const int nfull = m / ROWS;
+  const int GR = max(1, ngroups / (int)(32 * gridDim.x));
+  int item = 0, left = 0;
+  for (;;) {
+    if (left == 0) {
+      int b = 0;
+      if (lane == 0) b = atomicAdd(&st->work_ctr, GR);
+      item = __shfl(b, 0, 64);
+      left = GR;
+    } else {
+      ++item;
+    }
+    --left;
+    if (item >= ngroups) break;
+    const int t0 = item * C;
+    const int cnt = min(C, S - t0);
+    const T* col[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) col[c] = A + (size_t)sel_cols[t0 + min(c, cnt - 1)] * lda;
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = (T)0;
+    const int row_t = lane * VN;
+    int step = 0;
+    for (; step + U <= nfull; step += U) {
+      VA a[U][C], rv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int row = (step + u) * ROWS + row_t;
+        rv[u] = *reinterpret_cast<const VA*>(r + row);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          a[u][c] = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int e = 0; e < VN; ++e) acc[c] += a[u][c][e] * rv[u][e];
+    }
+    for (; step < nfull; ++step) {
+      const int row = step * ROWS + row_t;
+      const VA rv = *reinterpret_cast<const VA*>(r + row);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const VA a = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col[c] + row));
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[c] += a[e] * rv[e];
+      }
+    }
+    {
+      const int row = nfull * ROWS + row_t;
+      for (int e = 0; e < VN; ++e)
+        if (row + e < m) {
+          const T rr = r[row + e];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] += col[c][row + e] * rr;
+        }
+    }
+    T mine = (T)0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const T v = wave_sum(acc[c]);
+      if (lane == c) mine = v;
+    }
+    if (lane < cnt) {
+      const int t = t0 + lane;
+      const int j = sel_cols[t];
+      const T xj = x[j];
+      T g = mine - (T)bp.c2 * xj;
       if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
       const T q = (T)(cn2[j] + bp.tau);
       const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);

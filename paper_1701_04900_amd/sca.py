@@ -62,6 +62,17 @@ class sca_batch_item(ctypes.Structure):
                 ("instance", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class sca_launch(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("grad_kind", ctypes.c_int32),
+                ("grad_cols", ctypes.c_int32), ("grad_unroll", ctypes.c_int32),
+                ("grad_wg_per_cu", ctypes.c_int32)]
+
+
+class sca_tune_entry(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32), ("m_lo", ctypes.c_int64),
+                ("m_hi", ctypes.c_int64), ("launch", sca_launch)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _D = ctypes.c_double
@@ -88,6 +99,9 @@ SIGNATURES = {
                          _P]),
     "sca_profile_get": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D),
                              _S]),
+    "sca_tuning_set": (_S, [ctypes.POINTER(sca_tune_entry), _I64]),
+    "sca_problem_get_launch": (_S, [_P, ctypes.POINTER(sca_launch)]),
+    "sca_problem_set_launch": (_S, [_P, ctypes.POINTER(sca_launch)]),
     "sca_stream_copy": (_S, [_P, _P, _I64, ctypes.c_int32, _P]),
     "sca_stream_read": (_S, [_P, _I64, _P, ctypes.c_int32, _P]),
     "sca_batch_create": (_S, [ctypes.POINTER(_P), _S, _I64, ctypes.POINTER(sca_batch_item), _P]),
@@ -121,6 +135,7 @@ def lib():
             f.restype = res
             f.argtypes = args
         _LIB = L
+        load_tuning()
     return _LIB
 
 
@@ -157,6 +172,42 @@ def make_opts(gamma=0.9, tau=0.0, select_p=1.0, seed=0, instance=0, gamma_mu=0.0
               tol_merit=0.0) -> sca_opts:
     return sca_opts(ctypes.sizeof(sca_opts), gamma, gamma_mu, tau, select_p, seed, instance,
                     flags, max_rounds, check_every, refresh_every, tol_rel_obj, F_star, tol_merit)
+
+
+TUNING_PATH = os.path.join(_HERE, "tuning", "gfx950.json")
+
+
+def load_tuning(path=None):
+    """Install the launch-shape table written by paper_1701_04900_amd.autotune (if any)."""
+    import json
+    path = path or os.environ.get("SCA_TUNING", TUNING_PATH)
+    if not os.path.exists(path):
+        return 0
+    rows = json.load(open(path))["entries"]
+    arr = (sca_tune_entry * len(rows))()
+    for i, e in enumerate(rows):
+        arr[i] = sca_tune_entry(SCA_F32 if e["dtype"] == "f32" else SCA_F64, 0, e["m_lo"], e["m_hi"],
+                                sca_launch(ctypes.sizeof(sca_launch), e["grad_kind"],
+                                           e["grad_cols"], e["grad_unroll"], e["grad_wg_per_cu"]))
+    _check(_LIB.sca_tuning_set(arr, len(rows)))
+    return len(rows)
+
+
+def sca_tuning_set(rows):
+    arr = (sca_tune_entry * len(rows))(*rows)
+    _check(lib().sca_tuning_set(arr, len(rows)))
+
+
+def sca_problem_get_launch(h):
+    out = sca_launch()
+    _check(lib().sca_problem_get_launch(h, ctypes.byref(out)))
+    return dict(grad_kind=out.grad_kind, grad_cols=out.grad_cols, grad_unroll=out.grad_unroll,
+                grad_wg_per_cu=out.grad_wg_per_cu)
+
+
+def sca_problem_set_launch(h, grad_kind, grad_cols, grad_unroll, grad_wg_per_cu):
+    l = sca_launch(ctypes.sizeof(sca_launch), grad_kind, grad_cols, grad_unroll, grad_wg_per_cu)
+    _check(lib().sca_problem_set_launch(h, ctypes.byref(l)))
 
 
 # ------------------------------------------------------------------ entry points
