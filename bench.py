@@ -192,6 +192,111 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_grad_br_wg_lasso_20000x100000_fp32.txt")
+CALIB_BYTES = 1 << 30
+
+
+def kernel_fingerprint(launch):
+    """Digest of the round kernels' source and the launch shape the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sca_kernels.h", "sca_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1701_04900_amd", "csrc", f), "rb").read())
+    h.update(json.dumps(launch, sort_keys=True).encode())
+    return h.hexdigest()[:16]
+
+
+def pmc_probe(args):
+    """What the counter runs profile: three copies of exactly 1 GiB (the calibration), then
+    30 rounds of the 20000 x 100000 FP32 workload from x = 0."""
+    w = inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")
+    src = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        sca.sca_stream_copy(dst, src, CALIB_BYTES)
+    torch.cuda.synchronize()
+    del src, dst
+    P = sca.Problem.from_workload(w)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, max_rounds=30,
+                      check_every=10)
+    x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+    st = sca.sca_solve(P.handle, o, x)
+    print(json.dumps(dict(rounds=st["rounds"], coord_updates=st["coord_updates"],
+                          launch=sca.sca_problem_get_launch(P.handle), m=w.m)), flush=True)
+
+
+def pmc_summarize(fetch_dir, write_dir, probe_json):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the calibration copy and of the gradient
+    kernel -> bytes per launch, scaled so the copy reads and writes exactly 1 GiB."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+    probe = json.loads(open(probe_json).read().strip().splitlines()[-1])
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = load(d, counter)
+        copy = [v for k, v in vals.items() if "k_stream_copy" in k][0]
+        grad = [v for k, v in vals.items() if "k_grad_br" in k and "<float" in k][0]
+        cal = CALIB_BYTES / (sorted(copy)[len(copy) // 2] * 1024.0)
+        res[counter] = dict(copy_kib=sorted(copy)[len(copy) // 2], scale=cal,
+                            grad_kib_mean=sum(grad) / len(grad), launches=len(grad))
+    launches = res["FETCH_SIZE"]["launches"]
+    fetch_b = res["FETCH_SIZE"]["grad_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
+    write_b = res["WRITE_SIZE"]["grad_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
+    alg_b = probe["coord_updates"] / probe["rounds"] * probe["m"] * 4
+    fp = kernel_fingerprint(probe["launch"])
+    lines = [
+        "# HBM traffic of the gradient kernel, LASSO 20000x100000 FP32 (rocprofv3 counters)",
+        "",
+        "Commands (repository root, one MI355X; each counter in a run of its own):",
+        "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -- "
+        "python3 bench.py --pmc-probe > gpurun_out/pmc_probe.json",
+        "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -- "
+        "python3 bench.py --pmc-probe",
+        "  python bench.py --pmc-summarize gpurun_out/pmc_fetch gpurun_out/pmc_write "
+        "gpurun_out/pmc_probe.json",
+        "",
+        "Calibration: k_stream_copy moves exactly 1 GiB each way; the counters read "
+        f"{res['FETCH_SIZE']['copy_kib']:.0f} KiB fetched and {res['WRITE_SIZE']['copy_kib']:.0f} KiB "
+        f"written per copy, so the scale factors are {res['FETCH_SIZE']['scale']:.4f} (fetch) and "
+        f"{res['WRITE_SIZE']['scale']:.4f} (write).",
+        "",
+        f"launches: {launches}",
+        f"launch: {json.dumps(probe['launch'], sort_keys=True)}",
+        f"fingerprint: {fp}",
+        f"fetch_bytes_per_launch: {fetch_b:.0f}",
+        f"write_bytes_per_launch: {write_b:.0f}",
+        f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
+        f"algorithmic_bytes_per_launch: {alg_b:.0f}",
+        f"traffic_over_algorithmic: {(fetch_b + write_b) / alg_b:.4f}",
+    ]
+    open(PMC_SUMMARY, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def pmc_traffic(launch):
+    """Traffic per launch from the committed counter summary, or None when it is absent or
+    was taken on other kernel code or another launch shape."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(PMC_SUMMARY):
+        if ": " in line and not line.startswith(" "):
+            k, v = line.split(": ", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("fingerprint") != kernel_fingerprint(launch):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,7 +310,12 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", choices=["lasso", "batch"], default="lasso")
     ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_JSON"))
     args = ap.parse_args()
+    if args.pmc_summarize:
+        pmc_summarize(*args.pmc_summarize)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (column-block sharding with "
               "an all-reduce of the residual update per round) is not built", file=sys.stderr)
@@ -217,6 +327,9 @@ def main():
     sca.lib()
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.pmc_probe:
+        pmc_probe(args)
         return
 
     t0 = time.perf_counter()
@@ -281,8 +394,10 @@ def main():
                  1: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},true>",
                  2: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},false>",
                  3: f"k_grad_br_wwalk<float,{L['grad_cols']},{L['grad_unroll']}>"}[L["grad_kind"]]
+        traffic = pmc_traffic(L)
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic),
                     kernel=kname, launch=L, avg_launch_ms=round(avg_ms, 4),
                     alg_bytes_per_launch=round(bytes_total / g["launches"]))
         # achievable read bandwidth on the same 8 GB matrix: a plain 16-byte streaming read
