@@ -61,9 +61,14 @@ def cpu_baseline(w, opts_kw, rounds):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
-    At = w.At.cpu()
-    prob = O.Problem(A=At[:, : w.m].numpy().T, b=w.b.double().cpu().numpy(), lam=w.lam, c=w.c,
-                     beta=w.beta, block_ptr=w.block_ptr)
+    if hasattr(w, "rowptr"):
+        A = w.scipy_csr().tocsc()
+        what = f"{w.m}x{w.n} sparse FP32 LASSO ({w.nnz} nonzeros)"
+    else:
+        A = w.At.cpu()[:, : w.m].numpy().T
+        what = f"{w.m}x{w.n} FP32 {'box-nonconvex problem' if w.c else 'LASSO'}"
+    prob = O.Problem(A=A, b=w.b.double().cpu().numpy(), lam=w.lam, c=w.c, beta=w.beta,
+                     block_ptr=w.block_ptr)
     cfg = O.RunConfig(tau=opts_kw["tau"], gamma=opts_kw["gamma"], p=opts_kw["select_p"],
                       seed=opts_kw["seed"])
     prob.colnorm2()  # the per-problem set-up (the GPU side does it at create time)
@@ -73,7 +78,7 @@ def cpu_baseline(w, opts_kw, rounds):
     x, r, upd = O.run_rounds(prob, cfg, x, r, 0, rounds)
     dt = time.perf_counter() - t0
     return dict(value=upd / dt, unit="coord-updates/s", cores=int(threads), kind="oracle",
-                sample=f"{rounds} rounds from x=0 of the same {w.m}x{w.n} FP32 LASSO "
+                sample=f"{rounds} rounds from x=0 of the same {what} "
                        f"({upd} coordinate updates in {dt:.1f} s, FP64 numpy)")
 
 
@@ -308,7 +313,8 @@ def main():
     ap.add_argument("--cpu-rounds", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["lasso", "batch"], default="lasso")
+    ap.add_argument("--workload", choices=["lasso", "nonconvex", "sparse", "batch"],
+                    default="lasso")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_JSON"))
@@ -332,25 +338,92 @@ def main():
         pmc_probe(args)
         return
 
+    bench_single(args)
+
+
+def make_workload(kind, args):
+    if kind == "lasso":
+        return inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")
+    if kind == "nonconvex":
+        return inputs.nonconvex_box_fp32(seed=0, device="cuda")
+    return inputs.sparse_lasso_fp32(seed=0, device="cuda")
+
+
+def sparse_reference_optimum(w, opts_kw):
+    """F* by an FP64 solve of the stored FP32 CSR data (upcast copy) to merit <= 1e-12."""
+    P = sca.Problem.csr(w.m, w.n, w.rowptr, w.colidx, w.vals.double(), w.b.double(), w.lam,
+                        w.c, w.beta, w.block_ptr)
+    o = sca.make_opts(**opts_kw, max_rounds=200000, check_every=50, tol_merit=1e-12)
+    x = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    st = sca.sca_solve(P.handle, o, x, raise_on_notconv=False)
+    P.close()
+    torch.cuda.empty_cache()
+    return st["F"], st
+
+
+def grad_kernel_name(L, sparse):
+    if sparse:
+        return "k_grad_br_csc<float>"
+    return {0: f"k_grad_br<float,{L['grad_unroll']}>",
+            1: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},true>",
+            2: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},false>",
+            3: f"k_grad_br_wwalk<float,{L['grad_cols']},{L['grad_unroll']}>"}[L["grad_kind"]]
+
+
+def read_stream_peak(buf):
+    """Best of a plain 16-byte streaming read over `buf` (the matrix's own storage)."""
+    sink = torch.zeros(1 << 14, dtype=torch.float32, device="cuda")
+    nbytes = buf.numel() * buf.element_size() // 16 * 16
+    best = 0.0
+    for grid in (1024, 2048):
+        sca.sca_stream_read(buf, nbytes, sink, grid)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            sca.sca_stream_read(buf, nbytes, sink, grid)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 3 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    return best
+
+
+def bench_single(args):
+    """One problem, K timed solves from x = 0 to tolerance (LASSO: relative objective error
+    against F*; box-nonconvex: merit ||xhat(x) - x||_inf)."""
+    kind = args.workload
+    sparse = kind == "sparse"
     t0 = time.perf_counter()
-    w = inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")
+    w = make_workload(kind, args)
     torch.cuda.synchronize()
     log(f"generated {w.name} in {time.perf_counter() - t0:.1f} s: lam={w.lam:.4g} tau={w.tau:.4g}")
     opts_kw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+    esize = w.dtype.itemsize if hasattr(w.dtype, "itemsize") else torch.finfo(w.dtype).bits // 8
+    if sparse:
+        # every column holds the same number of nonzeros: value + int32 row index each
+        per_col = w.nnz // w.n
+        assert per_col * w.n == w.nnz
+        bytes_per_update = (esize + 4) * per_col
+    else:
+        bytes_per_update = w.m * esize
 
-    t0 = time.perf_counter()
-    F_star, st64 = reference_optimum(w, opts_kw)
-    log(f"F* = {F_star:.15g} (FP64 solve: {st64['rounds']} rounds, merit {st64['merit']:.2e}, "
-        f"{time.perf_counter() - t0:.1f} s)")
+    F_star = None
+    if kind == "nonconvex":
+        stop_kw = dict(tol_merit=args.tol)
+    else:
+        t0 = time.perf_counter()
+        F_star, st64 = (sparse_reference_optimum if sparse else reference_optimum)(w, opts_kw)
+        log(f"F* = {F_star:.15g} (FP64 solve: {st64['rounds']} rounds, merit "
+            f"{st64['merit']:.2e}, {time.perf_counter() - t0:.1f} s)")
+        stop_kw = dict(tol_rel_obj=args.tol, F_star=F_star)
 
     P = sca.Problem.from_workload(w)
-    opts = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
-                         F_star=F_star)
+    opts = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10, **stop_kw)
     x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
     for i in range(args.warmup):
         x.zero_()
         st = sca.sca_solve(P.handle, opts, x)
-        log(f"warmup solve {i}: {st['rounds']} rounds, rel err {st['rel_err']:.2e}")
+        log(f"warmup solve {i}: {st['rounds']} rounds, rel err {st['rel_err']:.2e}, "
+            f"merit {st['merit']:.2e}")
     # timed region: K solves, each check cycle one graph launch
     torch.cuda.synchronize()
     stats = []
@@ -371,8 +444,8 @@ def main():
     if not args.no_profile:
         # the same K solves again with HIP events around every kernel launch (eager launches
         # on the caller's stream: events cannot time kernels inside a replayed graph)
-        popts = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10,
-                              tol_rel_obj=args.tol, F_star=F_star, flags=sca.SCA_FLAG_PROFILE)
+        popts = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10, **stop_kw,
+                              flags=sca.SCA_FLAG_PROFILE)
         sca.sca_profile_get(P.handle, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -385,43 +458,32 @@ def main():
         prof = sca.sca_profile_get(P.handle, reset=True)
         pupd = sum(s["coord_updates"] for s in pst)
         pmoved = sum(s["moved_updates"] for s in pst)
-        g = prof["grad"]
-        bytes_total = float(pupd) * w.m * w.At.element_size()
-        avg_ms = g["ms"] / g["launches"]
-        achieved = bytes_total / (g["ms"] * 1e-3) / 1e9
         L = sca.sca_problem_get_launch(P.handle)
-        kname = {0: f"k_grad_br<float,{L['grad_unroll']}>",
-                 1: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},true>",
-                 2: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},false>",
-                 3: f"k_grad_br_wwalk<float,{L['grad_cols']},{L['grad_unroll']}>"}[L["grad_kind"]]
-        traffic = pmc_traffic(L)
+        g, f = prof["grad"], prof["fold"]
+        grad_b = float(pupd) * bytes_per_update
+        fold_b = float(pmoved) * bytes_per_update
+        cands = [("grad", g, grad_b, grad_kernel_name(L, sparse))]
+        if sparse:
+            cands.append(("fold", f, fold_b, "k_fold_csc<float> + k_fold_csc_finish<float>"))
+        step, kp, kb, kname = max(cands, key=lambda c: c[1]["ms"])
+        achieved = kb / (kp["ms"] * 1e-3) / 1e9
+        traffic = pmc_traffic(L) if kind == "lasso" and step == "grad" else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic),
-                    kernel=kname, launch=L, avg_launch_ms=round(avg_ms, 4),
-                    alg_bytes_per_launch=round(bytes_total / g["launches"]))
-        # achievable read bandwidth on the same 8 GB matrix: a plain 16-byte streaming read
-        sink = torch.zeros(1 << 14, dtype=torch.float32, device="cuda")
-        nbytes = w.At.numel() * w.At.element_size() // 16 * 16
-        best = 0.0
-        for grid in (1024, 2048):
-            sca.sca_stream_read(w.At, nbytes, sink, grid)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(3):
-                sca.sca_stream_read(w.At, nbytes, sink, grid)
-            e1.record()
-            torch.cuda.synchronize()
-            best = max(best, 3 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+                    kernel=kname, step=step, launch=L,
+                    avg_launch_ms=round(kp["ms"] / kp["launches"], 4),
+                    alg_bytes_per_launch=round(kb / kp["launches"]))
+        best = read_stream_peak(w.vals if sparse else w.At)
         roof["read_stream_peak"] = round(best, 1)
         roof["frac_of_read_stream_peak"] = round(achieved / best, 4)
-        fold_b = float(pmoved) * w.m * w.At.element_size()
-        f = prof["fold"]
         prof_pass = dict(ms_per_step=pel / args.steps * 1e3,
                          per_launch_ms={k: round(v["ms"] / max(1, v["launches"]), 4)
                                         for k, v in prof.items()},
+                         grad_GBps=round(grad_b / (g["ms"] * 1e-3) / 1e9, 1) if g["ms"] else None,
                          fold_GBps=round(fold_b / (f["ms"] * 1e-3) / 1e9, 1) if f["ms"] else None,
-                         moved_per_round=pmoved / max(1, sum(s["rounds"] for s in pst)))
+                         moved_per_round=pmoved / max(1, sum(s["rounds"] for s in pst)),
+                         bytes_per_update=bytes_per_update)
         log(f"profiled pass: {prof_pass}")
 
     cpu = None
@@ -430,6 +492,21 @@ def main():
         cpu = cpu_baseline(w, opts_kw, args.cpu_rounds)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f} s: {cpu}")
 
+    if kind == "lasso":
+        wname = f"lasso_dense_{w.m}x{w.n}_fp32"
+        block = 64
+    elif kind == "nonconvex":
+        wname = f"ncvx_box_{w.m}x{w.n}_fp32"
+        block = 32
+    else:
+        wname = f"sparse_lasso_{w.m}x{w.n}_nnz{w.nnz}_fp32"
+        block = 256
+    cfg = {"workload": wname, "m": w.m, "n": w.n, "block": block, "select_p": w.p,
+           "gamma": w.gamma, "tau": round(w.tau, 6), "step": "one solve from x=0 to tolerance"}
+    if kind == "nonconvex":
+        cfg.update(c=w.c, beta=w.beta, tol_merit=args.tol)
+    else:
+        cfg["tol_rel_obj"] = args.tol
     out = {
         "metric": METRIC,
         "value": value,
@@ -443,12 +520,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"lasso_dense_{w.m}x{w.n}_fp32", "m": w.m, "n": w.n, "block": 64,
-                   "select_p": w.p, "gamma": w.gamma, "tau": round(w.tau, 6),
-                   "tol_rel_obj": args.tol, "step": "one solve from x=0 to tolerance"},
+        "config": cfg,
         "time_to_tol_s": elapsed / args.steps,
         "rounds_per_solve": rounds / args.steps,
         "rel_err_final": [s["rel_err"] for s in stats],
+        "merit_final": [s["merit"] for s in stats],
         "F_star": F_star,
         "roofline": roof,
         "profiled_pass": prof_pass,

@@ -122,8 +122,10 @@ sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtype, int64_t 
 /* Create a problem over a sparse A given in CSR (row-major) form: rowptr_dev (m+1 int64),
  * colidx_dev (nnz int32 in [0,n)), vals_dev (nnz of the dtype), b_dev (m).  The library
  * builds and owns a column-major (CSC) copy with rows ascending inside each column; the
- * caller may free the CSR once this call returns.  Other arguments as for the dense form.
- * Synchronises 'stream'. */
+ * caller may free the CSR once this call returns.  Limits: 0 <= nnz < 2^31, m <= 2^23
+ * (SCA_EINVAL beyond); a repeated (row, column) entry or a column index outside [0, n) is
+ * SCA_EINVAL.  Device memory: the CSC copy plus a fold workspace of nnz entries (8 bytes
+ * each in FP32, 16 in FP64).  Other arguments as for the dense form.  Synchronises 'stream'. */
 sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype, int64_t m, int64_t n,
                                   int64_t nnz, const int64_t* rowptr_dev,
                                   const int32_t* colidx_dev, const void* vals_dev,

@@ -229,7 +229,8 @@ void sca::free_workspace(sca_problem* p) {
   void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state, p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
                   p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
                   p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
-                  p->csc_colptr, p->csc_rowidx, p->csc_vals, p->csr_tmp};
+                  p->csc_colptr, p->csc_rowidx, p->csc_vals, p->d_bin_cnt, p->d_bin_tot,
+                  p->d_bin_moved, p->d_ent};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   adjoint_release(p->adj);

@@ -1,12 +1,16 @@
 // Sparse path of libsca: A given in CSR is converted once to a library-owned CSC
-// (rows ascending inside every column); a round then reads, per drawn coordinate, the
-// nonzeros of its column (value + row index) and gathers r from L2.  The residual fold is
-// a scatter-add into r; it is accumulated in 128-bit fixed point with integer atomics, so
-// the sum is exact at 2^-72 resolution and independent of the order of the additions
-// (bitwise reproducible), then added to r in one rounding.
+// (rows ascending inside every column).  A round reads, per drawn coordinate, the nonzeros
+// of its column (value + row index) and gathers r from L2.  The residual fold is a
+// scatter-add into r, done without global atomics and bitwise reproducibly: rows are cut
+// into bins of R = 2^bin_log rows; the gradient kernel counts, per workgroup and bin, the
+// nonzeros of its moved columns; a scan turns the counts into slots; a scatter pass writes
+// (row within bin, a_ij * dx_j) entries into the slots; one workgroup per bin adds its
+// entries into fixed-point cells in LDS (exact at 2^-72, so the order of the additions
+// does not matter) and adds the cells to r in one rounding.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -16,7 +20,6 @@ using namespace sca;
 
 namespace {
 
-constexpr int kFixFrac = 72;  // fixed-point fraction bits: value = (hi * 2^64 + lo) * 2^-72
 
 // ------------------------------------------------------------------ CSR -> CSC
 __global__ void k_count_cols(const int32_t* __restrict__ colidx, long long nnz, int n,
@@ -91,8 +94,48 @@ __global__ void k_colnorm2_csc(const long long* __restrict__ colptr, const T* __
 }
 
 // ------------------------------------------------------------------ round kernels
-// 16 lanes per drawn coordinate (4 per wave): g_j = sum_k v_k r[row_k], then the best
-// response and the step (the same closed form as the dense path).
+constexpr int kBinMaxLog = 10;     // bins of at most 1024 rows: 32 KiB of limb cells
+constexpr int kBinMinLog = 6;
+constexpr int kMaxBins = 8192;     // histogram of a workgroup: 32 KiB of LDS
+constexpr int kCscThreads = 1024;  // 64 groups of 16 lanes; one listed column per group
+constexpr int kBinGridMax = 4096;  // workgroups of the counting kernels (scan: 16 per thread)
+
+// Exclusive scan over a block of NW waves; 'sh' needs NW + 1 ints.  Contains __syncthreads.
+template <int NW>
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < NW; ++w) {
+      const int t = sh[w];
+      sh[w] = run;
+      run += t;
+    }
+    sh[NW] = run;
+  }
+  __syncthreads();
+  const int res = sh[wave] + inc - v;
+  *total = sh[NW];
+  __syncthreads();
+  return res;
+}
+
+// Sum of 16 lanes (xor butterfly inside each aligned group of 16; every lane of the group
+// ends with the same, bitwise identical value).
+template <typename Acc> __device__ __forceinline__ Acc sum16(Acc s) {
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+  return s;
+}
+
 template <typename T, typename TR, typename Acc>
 __device__ __forceinline__ Acc csc_col_dot(const long long* __restrict__ colptr,
                                            const int* __restrict__ rowidx,
@@ -101,88 +144,468 @@ __device__ __forceinline__ Acc csc_col_dot(const long long* __restrict__ colptr,
   Acc s = (Acc)0;
   const long long b = colptr[j], e = colptr[j + 1];
   for (long long k = b + sub; k < e; k += 16) s += (Acc)v[k] * (Acc)r[rowidx[k]];
-#pragma unroll
-  for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
-  return s;
+  return sum16(s);
 }
 
+// Work mapping shared by the counting, gradient and scatter kernels: workgroup w takes the
+// contiguous chunk [c0, c1) of the S listed items (ceil(S / grid) each); inside it, groups
+// of 16 lanes take items c0 + group, c0 + group + groups, ...
+__device__ __forceinline__ void wg_chunk(int S, int* c0, int* c1) {
+  const long long per = ((long long)S + gridDim.x - 1) / gridDim.x;
+  const long long a = min((long long)S, (long long)blockIdx.x * per);
+  *c0 = (int)a;
+  *c1 = (int)min((long long)S, a + per);
+}
+
+__device__ __forceinline__ void flush_counts(const int* hist, int nb, int moved, int* s_moved,
+                                             int* __restrict__ cnt, int* __restrict__ moved_wg) {
+  const int wm = (int)wave_sum_i64((long long)moved);
+  if ((threadIdx.x & 63) == 0) s_moved[threadIdx.x >> 6] = wm;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) cnt[(size_t)blockIdx.x * nb + i] = hist[i];
+  if (threadIdx.x == 0 && moved_wg) {
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_moved[w];
+    moved_wg[blockIdx.x] = tot;
+  }
+}
+
+// Best response and step of drawn coordinate t (column j) from its dot product a_j^T r;
+// every lane of the group computes the same d, lane 0 stores.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ T csc_step(T dot, int j, int t, int sub, T gamma, T* __restrict__ x,
+                                      const double* __restrict__ cn2, T* __restrict__ dx_sel,
+                                      const BRParams& bp) {
+  const T xj = x[j];
+  T g = dot - (T)bp.c2 * xj;
+  if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+  const T q = (T)(cn2[j] + bp.tau);
+  const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
+  const T d = gamma * (xh - xj);
+  if (sub == 0) {
+    x[j] = xj + d;
+    dx_sel[t] = d;
+  }
+  return d;
+}
+
+// S.2 + S.4 on sparse columns with r gathered from memory (used when the panel kernel
+// below does not apply): 16 lanes per drawn coordinate; the first 16*U nonzeros are loaded
+// at once, longer columns continue in a loop.  The moved columns' nonzeros are counted per
+// row bin in LDS; the counts go to cnt[blockIdx.x][bin], the number of moved columns to
+// moved_wg[blockIdx.x].
+template <typename T, int U>
+__global__ void __launch_bounds__(kCscThreads)
 k_grad_br_csc(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
               const T* __restrict__ v, const T* __restrict__ r, T* __restrict__ x,
               const double* __restrict__ cn2, const int* __restrict__ sel_cols,
-              const RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp) {
+              const RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp,
+              int bin_log, int nb, int* __restrict__ cnt, int* __restrict__ moved_wg) {
+  extern __shared__ int hist[];
+  __shared__ int s_moved[kCscThreads / 64];
+  for (int i = threadIdx.x; i < nb; i += kCscThreads) hist[i] = 0;
+  __syncthreads();
   const int sub = threadIdx.x & 15;
-  const int S = st->S_cnt;
   const T gamma = (T)st->gamma_cur;
-  const int ngroup = gridDim.x * 16;
-  for (int t = blockIdx.x * 16 + (threadIdx.x >> 4); t < S; t += ngroup) {
+  int c0, c1;
+  wg_chunk(st->S_cnt, &c0, &c1);
+  int moved = 0;
+  for (int t = c0 + (int)(threadIdx.x >> 4); t < c1; t += kCscThreads / 16) {
     const int j = sel_cols[t];
-    const T dot = csc_col_dot<T, T, T>(colptr, rowidx, v, r, j, sub);
-    if (sub == 0) {
-      const T xj = x[j];
-      T g = dot - (T)bp.c2 * xj;
-      if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
-      const T q = (T)(cn2[j] + bp.tau);
-      const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
-      const T d = gamma * (xh - xj);
-      x[j] = xj + d;
-      dx_sel[t] = d;
+    const long long b = colptr[j], e = colptr[j + 1];
+    int ri[U];
+    T vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long k = b + sub + 16 * u;
+      ri[u] = k < e ? rowidx[k] : -1;
+      vv[u] = k < e ? v[k] : (T)0;
+    }
+    T s = (T)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ri[u] >= 0) s += vv[u] * r[ri[u]];
+    for (long long k = b + sub + 16 * U; k < e; k += 16) s += v[k] * r[rowidx[k]];
+    const T d = csc_step<T>(sum16(s), j, t, sub, gamma, x, cn2, dx_sel, bp);
+    if (d != (T)0) {
+      moved += sub == 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ri[u] >= 0) atomicAdd(&hist[ri[u] >> bin_log], 1);
+      for (long long k = b + sub + 16 * U; k < e; k += 16)
+        atomicAdd(&hist[rowidx[k] >> bin_log], 1);
+    }
+  }
+  flush_counts(hist, nb, moved, s_moved, cnt, moved_wg);
+}
+
+// S.2 + S.4 with r staged in LDS: one 1024-thread workgroup per CU walks the rows in
+// equal panels of at most 128 KiB; for each panel it copies r's panel into LDS (loads unrolled in batches
+// of 16 per thread and issued together with the column loads), then every group of 16
+// lanes advances a cursor through each of its columns (up to CPG per pass) over the
+// nonzeros whose rows fall in the panel (rows ascend inside a column, so they form a prefix
+// of each 32-entry window), with r read from LDS.  Each lane keeps its partial sums across
+// panels; the 16 partial sums of a column are added at the end in a fixed order.  Then the
+// best response, the step and the bin counts of the moved columns as in the kernel above.
+constexpr int kPanelBytes = 131072;
+constexpr int kPanelMaxBins = 2048;
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelGroups = kPanelThreads / 16;
+constexpr int kPanelBatch = 16;
+template <typename T, int CPG>
+__global__ void __launch_bounds__(kPanelThreads)
+k_grad_br_cscp(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
+               const T* __restrict__ v, const T* __restrict__ r, T* __restrict__ x,
+               const double* __restrict__ cn2, const int* __restrict__ sel_cols,
+               const RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp, int m,
+               int bin_log, int nb, int* __restrict__ cnt, int* __restrict__ moved_wg) {
+  constexpr int PR = kPanelBytes / (int)sizeof(T);
+  __shared__ T s_r[PR];
+  __shared__ int hist[kPanelMaxBins];
+  __shared__ int s_moved[kPanelThreads / 64];
+  for (int i = threadIdx.x; i < nb; i += kPanelThreads) hist[i] = 0;
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int gshift = 16 * ((threadIdx.x & 63) >> 4);
+  const T gamma = (T)st->gamma_cur;
+  int c0, c1;
+  wg_chunk(st->S_cnt, &c0, &c1);
+  // equal panels of at most PR rows (multiples of 64)
+  const int NP = (m + PR - 1) / PR;
+  const int PE = ((m + NP - 1) / NP + 63) / 64 * 64;
+  int moved = 0;
+  for (int pb = c0; pb < c1; pb += kPanelGroups * CPG) {
+    int kc[CPG], ke[CPG], jj[CPG];
+    T acc[CPG];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int t = pb + grp + kPanelGroups * i;
+      jj[i] = -1;
+      kc[i] = ke[i] = 0;
+      acc[i] = (T)0;
+      if (t < c1) {
+        jj[i] = sel_cols[t];
+        kc[i] = (int)colptr[jj[i]];
+        ke[i] = (int)colptr[jj[i] + 1];
+      }
+    }
+    for (int P = 0; P < NP; ++P) {
+      const int lo = P * PE, hi = min(m, lo + PE), len = hi - lo;
+      // the next 32 entries of every column
+      int rw[CPG][2];
+      T vw[CPG][2];
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = kc[i] + sub + 16 * h;
+          rw[i][h] = k < ke[i] ? rowidx[k] : INT_MAX;
+          vw[i][h] = k < ke[i] ? v[k] : (T)0;
+        }
+      }
+      // r's panel into LDS: a batch of loads per thread, then (after every wave has left
+      // the previous panel) the stores
+      for (int base = 0; base < len; base += kPanelThreads * kPanelBatch) {
+        T tmp[kPanelBatch];
+#pragma unroll
+        for (int u = 0; u < kPanelBatch; ++u) {
+          const int i = base + (int)threadIdx.x + u * kPanelThreads;
+          tmp[u] = i < len ? r[lo + i] : (T)0;
+        }
+        if (base == 0) __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPanelBatch; ++u) {
+          const int i = base + (int)threadIdx.x + u * kPanelThreads;
+          if (i < len) s_r[i] = tmp[u];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+        int nin = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool in = rw[i][h] < hi;
+          if (in) acc[i] += vw[i][h] * s_r[rw[i][h] - lo];
+          nin += __popcll((__ballot(in) >> gshift) & 0xffffull);
+        }
+        kc[i] += nin;
+        while (nin == 32) {  // the whole window was inside the panel: next window
+          nin = 0;
+          for (int h = 0; h < 2; ++h) {
+            const int k = kc[i] + sub + 16 * h;
+            const int rr = k < ke[i] ? rowidx[k] : INT_MAX;
+            const bool in = rr < hi;
+            if (in) acc[i] += v[k] * s_r[rr - lo];
+            nin += __popcll((__ballot(in) >> gshift) & 0xffffull);
+          }
+          kc[i] += nin;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      if (jj[i] < 0) continue;
+      const int t = pb + grp + kPanelGroups * i;
+      const T d = csc_step<T>(sum16(acc[i]), jj[i], t, sub, gamma, x, cn2, dx_sel, bp);
+      if (d != (T)0) {
+        moved += sub == 0;
+        for (long long k = colptr[jj[i]] + sub; k < ke[i]; k += 16)
+          atomicAdd(&hist[rowidx[k] >> bin_log], 1);
+      }
+    }
+    __syncthreads();  // the next pass refills the panels
+  }
+  __syncthreads();
+  flush_counts(hist, nb, moved, s_moved, cnt, moved_wg);
+}
+
+// Bin counts of the nonzeros of the columns j < n with coef[j] != 0 (same work mapping as
+// the gradient kernels; used for a fresh residual).
+template <typename T>
+__global__ void __launch_bounds__(kCscThreads)
+k_bin_hist(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
+           const T* __restrict__ coef, int n, int bin_log, int nb, int* __restrict__ cnt) {
+  extern __shared__ int hist[];
+  __shared__ int s_moved[kCscThreads / 64];
+  for (int i = threadIdx.x; i < nb; i += kCscThreads) hist[i] = 0;
+  __syncthreads();
+  const int sub = threadIdx.x & 15;
+  int c0, c1;
+  wg_chunk(n, &c0, &c1);
+  for (int j = c0 + (int)(threadIdx.x >> 4); j < c1; j += kCscThreads / 16) {
+    if (coef[j] == (T)0) continue;
+    for (long long k = colptr[j] + sub; k < colptr[j + 1]; k += 16)
+      atomicAdd(&hist[rowidx[k] >> bin_log], 1);
+  }
+  __syncthreads();
+  flush_counts(hist, nb, 0, s_moved, cnt, nullptr);
+}
+
+// cnt[w][bin] -> exclusive prefix over w inside each bin; tot[bin] = bin total.  One
+// workgroup per bin; thread i takes a run of consecutive w (all its loads in flight at
+// once), then a block scan orders the runs.  Block 0 also adds the moved columns of the
+// round to the running statistics.
+template <int PER>
+__global__ void __launch_bounds__(256)
+k_bin_scan(int* __restrict__ cnt, int grid, int nb, int* __restrict__ tot,
+           const int* __restrict__ moved_wg, RoundState* __restrict__ st) {
+  __shared__ int sh[5];
+  __shared__ long long s_mv[4];
+  const int bin = blockIdx.x;
+  const int w0 = threadIdx.x * PER;
+  int c[PER];
+  int sum = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    c[u] = w0 + u < grid ? cnt[(size_t)(w0 + u) * nb + bin] : 0;
+    sum += c[u];
+  }
+  int total;
+  int run = block_exclusive_scan<4>(sum, sh, &total);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (w0 + u < grid) cnt[(size_t)(w0 + u) * nb + bin] = run;
+    run += c[u];
+  }
+  if (threadIdx.x == 0) tot[bin] = total;
+  if (blockIdx.x == 0 && moved_wg) {
+    long long mv = 0;
+    for (int w = threadIdx.x; w < grid; w += 256) mv += moved_wg[w];
+    mv = wave_sum_i64(mv);
+    if ((threadIdx.x & 63) == 0) s_mv[threadIdx.x >> 6] = mv;
+    __syncthreads();
+    if (threadIdx.x == 0) st->moved_updates += s_mv[0] + s_mv[1] + s_mv[2] + s_mv[3];
+  }
+}
+
+// Start of every bin's slots (exclusive scan of tot) into base[0..nb); 256 threads.
+__device__ __forceinline__ void bin_starts(const int* __restrict__ tot, int nb, int* base,
+                                           int* sh) {
+  const int per = (nb + kCscThreads - 1) / kCscThreads;
+  const int i0 = min(nb, (int)threadIdx.x * per), i1 = min(nb, i0 + per);
+  int loc = 0;
+  for (int i = i0; i < i1; ++i) loc += tot[i];
+  int total;
+  int run = block_exclusive_scan<kCscThreads / 64>(loc, sh, &total);
+  for (int i = i0; i < i1; ++i) {
+    base[i] = run;
+    run += tot[i];
+  }
+}
+
+// One fold entry: row inside its bin and the product a_ij * dx_j, stored with one 8-byte
+// (FP32) or 16-byte (FP64) write.
+template <typename T> struct Ent;
+template <> struct alignas(8) Ent<float> {
+  uint32_t row;
+  float val;
+};
+template <> struct alignas(16) Ent<double> {
+  uint64_t row;
+  double val;
+};
+__device__ __forceinline__ void put_ent(Ent<float>* e, long long pos, uint32_t row, float val) {
+  reinterpret_cast<uint2*>(e)[pos] = make_uint2(row, __float_as_uint(val));
+}
+__device__ __forceinline__ void put_ent(Ent<double>* e, long long pos, uint32_t row, double val) {
+  reinterpret_cast<ulonglong2*>(e)[pos] =
+      make_ulonglong2((unsigned long long)row, (unsigned long long)__double_as_longlong(val));
+}
+
+// Writes the entries (row within bin, a_ij * coef) of the listed columns with coef != 0
+// into their bins' slots.  list == nullptr: the columns 0..count-1 with coef indexed by j;
+// otherwise list[t] with coef indexed by t.  Same work mapping as the counting kernel; a
+// column's nonzeros are loaded 16*U at a time before their slots are taken.
+template <typename T, int U>
+__global__ void __launch_bounds__(kCscThreads)
+k_bin_scatter(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
+              const T* __restrict__ v, const int* __restrict__ list,
+              const int* __restrict__ count_ptr, int count, const T* __restrict__ coef,
+              int bin_log, int nb, const int* __restrict__ off, const int* __restrict__ tot,
+              Ent<T>* __restrict__ ent) {
+  extern __shared__ int cursor[];
+  __shared__ int sh[kCscThreads / 64 + 1];
+  bin_starts(tot, nb, cursor, sh);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kCscThreads) cursor[i] += off[(size_t)blockIdx.x * nb + i];
+  __syncthreads();
+  const int sub = threadIdx.x & 15;
+  const uint32_t rmask = (1u << bin_log) - 1u;
+  int c0, c1;
+  wg_chunk(count_ptr ? *count_ptr : count, &c0, &c1);
+  for (int t = c0 + (int)(threadIdx.x >> 4); t < c1; t += kCscThreads / 16) {
+    const int j = list ? list[t] : t;
+    const T d = coef[t];
+    if (d == (T)0) continue;
+    const long long b = colptr[j], e = colptr[j + 1];
+    for (long long k0 = b; k0 < e; k0 += 16 * U) {
+      int ri[U];
+      T vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long k = k0 + sub + 16 * u;
+        ri[u] = k < e ? rowidx[k] : -1;
+        vv[u] = k < e ? v[k] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ri[u] >= 0) {
+          const int pos = atomicAdd(&cursor[ri[u] >> bin_log], 1);
+          put_ent(ent, pos, (uint32_t)ri[u] & rmask, vv[u] * d);
+        }
+      }
     }
   }
 }
 
-// Exact fixed-point accumulation of a double into a 128-bit two's-complement cell
-// (cell[0] = low 64 bits, cell[1] = high 64 bits; unit 2^-72).  |val| is split into an
-// integer part (units of 2^-8) and an exact fraction, negated in 128 bits when val < 0;
-// the carry out of the low word is derived from the value the atomic returns, so the
-// final cell is the exact sum whatever the order of the additions.
-__device__ __forceinline__ void fix_add(unsigned long long* cell, double val) {
-  const double a = ldexp(fabs(val), kFixFrac - 64);
-  const double hi_d = floor(a);
-  unsigned long long hi = (unsigned long long)hi_d;
-  unsigned long long lo = (unsigned long long)ldexp(a - hi_d, 64);
-  if (val < 0.0) {
-    lo = ~lo + 1ull;
-    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+// Exact fixed-point accumulation in limbs: a row's cell is four signed 64-bit limbs with
+// weights 2^(32k) (k = 0..3) in units of 2^-72, stored limb-major (limb k of row r at
+// k * R + r, so the lanes of a wave spread over the LDS banks).  An entry's magnitude, an integer mantissa
+// M times a power of two, is placed at bit s = exponent + 72 (bits below the unit are
+// truncated toward zero) and split into 32-bit chunks, each added to its limb with a
+// non-returning LDS atomic; a limb takes 2^31 such additions before it can overflow.
+// Integer sums do not depend on the order of the additions; carries are resolved once
+// when the cell is read.  Magnitudes up to 2^55 per row are represented.
+constexpr int kLimbs = 4;
+__device__ __forceinline__ void limb_add(long long* cell, int R, unsigned long long M, int s,
+                                         bool neg) {
+  if (s < 0) {
+    if (s <= -64) return;
+    M >>= -s;
+    s = 0;
   }
-  if (lo == 0ull && hi == 0ull) return;
-  const unsigned long long old = atomicAdd(&cell[0], lo);
-  const unsigned long long h = hi + ((old + lo < old) ? 1ull : 0ull);
-  if (h != 0ull) atomicAdd(&cell[1], h);
+  if (M == 0ull) return;
+  int k = s >> 5;
+  const int o = s & 31;
+  // M < 2^53 and o < 32: M << o spans at most three 32-bit chunks
+  const unsigned long long lo = M << o;
+  const unsigned long long hi = o ? (M >> (64 - o)) : 0ull;
+  const unsigned long long ch[3] = {lo & 0xffffffffull, lo >> 32, hi};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (ch[i] == 0ull) continue;
+    long long c = (long long)ch[i];
+    int kk = k + i;
+    if (kk >= kLimbs) {  // beyond the represented range: fold into the top limb (or drop)
+      if (kk > kLimbs) continue;
+      c <<= 32;
+      kk = kLimbs - 1;
+    }
+    atomicAdd((unsigned long long*)&cell[kk * R], (unsigned long long)(neg ? -c : c));
+  }
+}
+__device__ __forceinline__ void limb_add_val(long long* cell, int R, float v) {
+  const uint32_t u = __float_as_uint(v);
+  const int ex = (int)((u >> 23) & 0xffu);
+  if (ex == 0) return;  // zero or subnormal: below the unit
+  const unsigned long long M = (unsigned long long)((u & 0x7fffffu) | 0x800000u);
+  limb_add(cell, R, M, ex - 127 - 23 + 72, (u >> 31) != 0u);
+}
+__device__ __forceinline__ void limb_add_val(long long* cell, int R, double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int ex = (int)((u >> 52) & 0x7ffull);
+  if (ex == 0) return;
+  const unsigned long long M = (u & 0xfffffffffffffull) | (1ull << 52);
+  limb_add(cell, R, M, ex - 1023 - 52 + 72, (u >> 63) != 0ull);
+}
+// Value of a cell in one rounding from its 128-bit two's-complement integer.
+__device__ __forceinline__ double limb_value(const long long* cell, int R) {
+  long long t = cell[0];
+  const unsigned long long c0 = (unsigned long long)t & 0xffffffffull;
+  t = cell[R] + (t >> 32);
+  const unsigned long long c1 = (unsigned long long)t & 0xffffffffull;
+  t = cell[2 * R] + (t >> 32);
+  const unsigned long long c2 = (unsigned long long)t & 0xffffffffull;
+  t = cell[3 * R] + (t >> 32);
+  const long long hi = (long long)(((unsigned long long)t << 32) | c2);
+  const unsigned long long lo = (c1 << 32) | c0;
+  return ldexp((double)hi, 64 - 72) + ldexp((double)lo, -72);
 }
 
-// 16 lanes per listed column: every nonzero adds a_ij * d_j to the cell of row i.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_fold_csc(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
-           const T* __restrict__ v, const int* __restrict__ J_idx, const T* __restrict__ J_val,
-           const RoundState* __restrict__ st, unsigned long long* __restrict__ acc) {
-  const int sub = threadIdx.x & 15;
-  const int J = st->J_cnt;
-  const int ngroup = gridDim.x * 16;
-  for (int e = blockIdx.x * 16 + (threadIdx.x >> 4); e < J; e += ngroup) {
-    const int j = J_idx[e];
-    const double d = (double)J_val[e];
-    for (long long k = colptr[j] + sub; k < colptr[j + 1]; k += 16)
-      fix_add(acc + 2 * (size_t)rowidx[k], (double)v[k] * d);
+// One workgroup per bin: the bin's entries are summed into limb cells in LDS (eight entry
+// loads per thread in flight), then out[i] = base_scale * base[i] + cell_i for the bin's
+// rows (one rounding; out may alias base; out and out64 may each be NULL).
+constexpr int kAccThreads = 1024;
+constexpr int kAccUnroll = 8;
+template <typename T, typename TB, typename TO>
+__global__ void __launch_bounds__(kAccThreads)
+k_bin_acc(const Ent<T>* __restrict__ ent, const int* __restrict__ tot, int bin_log, int m,
+          const TB* base, double base_scale, TO* out, double* __restrict__ out64) {
+  extern __shared__ long long cells[];
+  __shared__ long long s_part[kAccThreads / 64];
+  const int R = 1 << bin_log;
+  const int bin = blockIdx.x;
+  for (int i = threadIdx.x; i < kLimbs * R; i += kAccThreads) cells[i] = 0;
+  long long pre = 0;
+  for (int i = threadIdx.x; i < bin; i += kAccThreads) pre += tot[i];
+  pre = wave_sum_i64(pre);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = pre;
+  __syncthreads();
+  long long start = 0;
+  for (int w = 0; w < kAccThreads / 64; ++w) start += s_part[w];
+  const long long end = start + tot[bin];
+  for (long long e0 = start + threadIdx.x; e0 < end; e0 += kAccThreads * kAccUnroll) {
+    Ent<T> en[kAccUnroll];
+#pragma unroll
+    for (int u = 0; u < kAccUnroll; ++u) {
+      const long long e = e0 + (long long)u * kAccThreads;
+      if (e < end) {
+        en[u] = ent[e];
+      } else {
+        en[u].row = 0;
+        en[u].val = (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kAccUnroll; ++u) limb_add_val(&cells[(int)en[u].row], R, en[u].val);
   }
-}
-
-// out[i] = base_scale*base[i] + cell_i (one rounding); clears the cells for the next use.
-template <typename TB, typename TO>
-__global__ void __launch_bounds__(256)
-k_fold_csc_finish(const TB* __restrict__ base, double base_scale, unsigned long long* acc, int m,
-                  TO* __restrict__ out, double* __restrict__ out64) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-    const unsigned long long lo = acc[2 * (size_t)i];
-    const long long hi = (long long)acc[2 * (size_t)i + 1];
-    acc[2 * (size_t)i] = 0ull;
-    acc[2 * (size_t)i + 1] = 0ull;
-    const double add = ldexp((double)hi, 64 - kFixFrac) + ldexp((double)lo, -kFixFrac);
-    const double s = base_scale * (double)base[i] + add;
-    if (out) out[i] = (TO)s;
-    if (out64) out64[i] = s;
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += kAccThreads) {
+    const int row = bin * R + i;
+    if (row >= m) break;
+    const double s = base_scale * (double)base[row] + limb_value(&cells[i], R);
+    if (out) out[row] = (TO)s;
+    if (out64) out64[row] = s;
   }
 }
 
@@ -223,59 +646,91 @@ k_probe_csc(const long long* __restrict__ colptr, const int* __restrict__ rowidx
   }
 }
 
+// Bin scan, scatter and accumulation of a fold whose counts are in p->d_bin_cnt.
+template <typename T, typename TB, typename TO>
+void bin_fold(sca_problem* p, const int* list, const int* count_ptr, int count, const T* coef,
+              const int* moved_wg, const TB* base, double base_scale, TO* out, double* out64,
+              hipStream_t s) {
+  const int nb = p->bin_nb, grid = p->bin_grid;
+  if (grid <= 256 * 4)
+    hipLaunchKernelGGL(k_bin_scan<4>, dim3(nb), dim3(256), 0, s, p->d_bin_cnt, grid, nb,
+                       p->d_bin_tot, moved_wg, p->d_state);
+  else
+    hipLaunchKernelGGL(k_bin_scan<kBinGridMax / 256>, dim3(nb), dim3(256), 0, s, p->d_bin_cnt,
+                       grid, nb, p->d_bin_tot, moved_wg, p->d_state);
+  if (p->bin_unroll == 2)
+    hipLaunchKernelGGL((k_bin_scatter<T, 2>), dim3(grid), dim3(kCscThreads), sizeof(int) * nb, s,
+                       (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
+                       (const T*)p->csc_vals, list, count_ptr, count, coef, p->bin_log, nb,
+                       (const int*)p->d_bin_cnt, (const int*)p->d_bin_tot, (Ent<T>*)p->d_ent);
+  else if (p->bin_unroll == 4)
+    hipLaunchKernelGGL((k_bin_scatter<T, 4>), dim3(grid), dim3(kCscThreads), sizeof(int) * nb, s,
+                       (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
+                       (const T*)p->csc_vals, list, count_ptr, count, coef, p->bin_log, nb,
+                       (const int*)p->d_bin_cnt, (const int*)p->d_bin_tot, (Ent<T>*)p->d_ent);
+  else
+    hipLaunchKernelGGL((k_bin_scatter<T, 8>), dim3(grid), dim3(kCscThreads), sizeof(int) * nb, s,
+                       (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
+                       (const T*)p->csc_vals, list, count_ptr, count, coef, p->bin_log, nb,
+                       (const int*)p->d_bin_cnt, (const int*)p->d_bin_tot, (Ent<T>*)p->d_ent);
+  hipLaunchKernelGGL((k_bin_acc<T, TB, TO>), dim3(nb), dim3(kAccThreads),
+                     sizeof(long long) * kLimbs * ((size_t)1 << p->bin_log), s,
+                     (const Ent<T>*)p->d_ent, (const int*)p->d_bin_tot, p->bin_log, (int)p->m,
+                     base, base_scale, out, out64);
+}
+
+template <typename T, int U>
+void grad_launch(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream_t s) {
+  hipLaunchKernelGGL((k_grad_br_csc<T, U>), dim3(p->bin_grid), dim3(kCscThreads),
+                     sizeof(int) * p->bin_nb, s, (const long long*)p->csc_colptr,
+                     (const int*)p->csc_rowidx, (const T*)p->csc_vals, r, x, p->d_cn2,
+                     p->d_sel_cols, (const RoundState*)p->d_state, (T*)p->d_dx_sel, bp,
+                     p->bin_log, p->bin_nb, p->d_bin_cnt, p->d_bin_moved);
+}
+
 template <typename T>
-void fold_launch(sca_problem* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_fold_csc<T>, dim3(8 * p->ncu), dim3(256), 0, s,
-                     (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
-                     (const T*)p->csc_vals, (const int*)p->d_J_idx, (const T*)p->d_J_val,
-                     (const RoundState*)p->d_state, (unsigned long long*)p->csr_tmp);
+void grad_any(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream_t s) {
+  if (p->bin_panel) {
+    hipLaunchKernelGGL((k_grad_br_cscp<T, sizeof(T) == 4 ? 8 : 4>), dim3(p->bin_grid),
+                       dim3(kPanelThreads), 0, s,
+                       (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
+                       (const T*)p->csc_vals, r, x, p->d_cn2, p->d_sel_cols,
+                       (const RoundState*)p->d_state, (T*)p->d_dx_sel, bp, (int)p->m,
+                       p->bin_log, p->bin_nb, p->d_bin_cnt, p->d_bin_moved);
+  } else if (p->bin_unroll == 2) {
+    grad_launch<T, 2>(p, x, r, bp, s);
+  } else if (p->bin_unroll == 4) {
+    grad_launch<T, 4>(p, x, r, bp, s);
+  } else {
+    grad_launch<T, 8>(p, x, r, bp, s);
+  }
 }
 
 template <typename T>
 void round_csc(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s, uint64_t Tthr,
                const BRParams& bp) {
-  const int m = (int)p->m, n = (int)p->n;
   prof_begin(p, s, SCA_K_SELECT);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)p->nblocks, p->d_bp, o->seed,
                      o->instance, Tthr, p->d_state, p->d_sel_cols);
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_GRAD);
-  hipLaunchKernelGGL(k_grad_br_csc<T>, dim3(8 * p->ncu), dim3(256), 0, s,
-                     (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
-                     (const T*)p->csc_vals, (const T*)r, x, p->d_cn2, p->d_sel_cols,
-                     (const RoundState*)p->d_state, (T*)p->d_dx_sel, bp);
-  prof_end(p, s, 0.0);
-  prof_begin(p, s, SCA_K_COMPACT);
-  const int nch = (n + kChunk - 1) / kChunk;
-  const int cgrid = std::max(1, std::min(nch, 2 * p->ncu));
-  int* S_ptr = (int*)((char*)p->d_state + offsetof(RoundState, S_cnt));
-  hipLaunchKernelGGL(k_compact_count<T>, dim3(cgrid), dim3(1024), 0, s, (const T*)p->d_dx_sel,
-                     (const int*)S_ptr, p->d_chunk_cnt);
-  hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s,
-                     (const T*)p->d_dx_sel, (const int*)p->d_sel_cols, (const int*)S_ptr,
-                     (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val, p->d_state, 1);
+  grad_any<T>(p, x, r, bp, s);
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_FOLD);
-  fold_launch<T>(p, s);
-  hipLaunchKernelGGL((k_fold_csc_finish<T, T>), dim3((m + 255) / 256), dim3(256), 0, s,
-                     (const T*)r, 1.0, (unsigned long long*)p->csr_tmp, m, r, (double*)nullptr);
+  int* S_ptr = (int*)((char*)p->d_state + offsetof(RoundState, S_cnt));
+  bin_fold<T, T, T>(p, p->d_sel_cols, S_ptr, 0, (const T*)p->d_dx_sel, p->d_bin_moved, r, 1.0,
+                    r, (double*)nullptr, s);
   prof_end(p, s, 0.0);
 }
 
 template <typename T>
 void residual_csc(sca_problem* p, const T* x, T* r_out, hipStream_t s) {
-  const int m = (int)p->m, n = (int)p->n;
-  int* N_ptr = (int*)((char*)p->d_state + offsetof(RoundState, n_all));
-  const int nch = (n + kChunk - 1) / kChunk;
-  const int cgrid = std::max(1, std::min(nch, 2 * p->ncu));
-  hipLaunchKernelGGL(k_compact_count<T>, dim3(cgrid), dim3(1024), 0, s, x, (const int*)N_ptr,
-                     p->d_chunk_cnt);
-  hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s, x, (const int*)nullptr,
-                     (const int*)N_ptr, (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val,
-                     p->d_state, 0);
-  fold_launch<T>(p, s);
-  hipLaunchKernelGGL((k_fold_csc_finish<T, T>), dim3((m + 255) / 256), dim3(256), 0, s,
-                     (const T*)p->b, -1.0, (unsigned long long*)p->csr_tmp, m, r_out, p->d_r64);
+  hipLaunchKernelGGL(k_bin_hist<T>, dim3(p->bin_grid), dim3(kCscThreads),
+                     sizeof(int) * p->bin_nb, s, (const long long*)p->csc_colptr,
+                     (const int*)p->csc_rowidx, x, (int)p->n, p->bin_log, p->bin_nb,
+                     p->d_bin_cnt);
+  bin_fold<T, T, T>(p, (const int*)nullptr, (const int*)nullptr, (int)p->n, x,
+                    (const int*)nullptr, (const T*)p->b, -1.0, r_out, p->d_r64, s);
 }
 
 }  // namespace
@@ -344,7 +799,11 @@ static sca_status build_csc(sca_problem* p, const long long* rowptr, const int32
       (st = dev_alloc((void**)&p->csc_colptr, sizeof(long long) * (size_t)(n + 1))) != SCA_OK ||
       (st = dev_alloc((void**)&p->csc_rowidx, sizeof(int) * (size_t)std::max(1ll, nnz))) != SCA_OK ||
       (st = dev_alloc((void**)&p->csc_vals, sizeof(T) * (size_t)std::max(1ll, nnz))) != SCA_OK ||
-      (st = dev_alloc((void**)&p->csr_tmp, 16 * (size_t)p->ldp)) != SCA_OK) {
+      (st = dev_alloc((void**)&p->d_bin_cnt,
+                      sizeof(int) * (size_t)p->bin_grid * p->bin_nb)) != SCA_OK ||
+      (st = dev_alloc((void**)&p->d_bin_tot, sizeof(int) * (size_t)p->bin_nb)) != SCA_OK ||
+      (st = dev_alloc((void**)&p->d_bin_moved, sizeof(int) * (size_t)p->bin_grid)) != SCA_OK ||
+      (st = dev_alloc((void**)&p->d_ent, sizeof(Ent<T>) * (size_t)std::max(1ll, nnz))) != SCA_OK) {
     cleanup();
     return st;
   }
@@ -367,7 +826,6 @@ static sca_status build_csc(sca_problem* p, const long long* rowptr, const int32
     }
   (void)hipMemsetAsync(colcnt, 0, sizeof(int) * (size_t)(n + 1), s);
   (void)hipMemsetAsync(flags, 0, sizeof(int) * 4, s);
-  (void)hipMemsetAsync(p->csr_tmp, 0, 16 * (size_t)p->ldp, s);
   const int g = 8 * p->ncu;
   hipLaunchKernelGGL(k_count_cols, dim3(g), dim3(256), 0, s, colidx, nnz, n, colcnt, flags);
   std::vector<int> hc(n + 1);
@@ -417,8 +875,11 @@ extern "C" sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype,
   *out = nullptr;
   sca_status st = validate_problem_args(dtype, m, n, b, lambda, c, beta, block_ptr, nblocks);
   if (st != SCA_OK) return st;
-  if (nnz < 0 || nnz > (int64_t)INT32_MAX * 8)
-    return set_error(SCA_EINVAL, "nnz out of range");
+  if (nnz < 0 || nnz > (int64_t)INT32_MAX)
+    return set_error(SCA_EINVAL, "nnz out of range [0, 2^31)");
+  if (m > ((int64_t)kMaxBins << kBinMaxLog))
+    return set_error(SCA_EINVAL, "the sparse path takes m <= %lld rows",
+                     (long long)((int64_t)kMaxBins << kBinMaxLog));
   if (!rowptr || (nnz > 0 && (!colidx || !vals)))
     return set_error(SCA_EINVAL, "rowptr, colidx or vals is NULL");
   sca_problem* p = new (std::nothrow) sca_problem();
@@ -437,6 +898,15 @@ extern "C" sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype,
   p->sparse = true;
   p->nnz = nnz;
   p->ncu = device_cu_count();
+  // bins of R = 2^bin_log rows, at most 128 bins while 64 <= R <= 1024
+  int lg = kBinMinLog;
+  while (lg < kBinMaxLog && ((int64_t)1 << lg) * 128 < m) ++lg;
+  p->bin_log = lg;
+  p->bin_nb = (int)((m + ((int64_t)1 << lg) - 1) >> lg);
+  p->bin_grid = std::min(kBinGridMax, p->ncu);
+  p->bin_panel = p->bin_nb <= kPanelMaxBins && nnz < ((int64_t)1 << 31);
+  const double per_col = n > 0 ? (double)nnz / (double)n : 0.0;
+  p->bin_unroll = per_col <= 32.0 ? 2 : per_col <= 64.0 ? 4 : 8;
   hipStream_t s = (hipStream_t)stream;
   if ((st = alloc_workspace(p, block_ptr)) == SCA_OK) {
     st = dtype == SCA_F32

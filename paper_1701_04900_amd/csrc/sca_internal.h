@@ -35,7 +35,14 @@ struct sca_problem {
   long long* csc_colptr = nullptr;
   int* csc_rowidx = nullptr;
   void* csc_vals = nullptr;
-  void* csr_tmp = nullptr;
+  // binned fold: rows in bins of 2^bin_log; counts per (workgroup, bin) of the gradient
+  // grid, bin totals, moved columns per workgroup, and up to nnz (row, value) entries
+  int bin_log = 0, bin_nb = 0, bin_grid = 0, bin_unroll = 8;
+  bool bin_panel = true;  // gradient with r staged in LDS panels
+  int* d_bin_cnt = nullptr;
+  int* d_bin_tot = nullptr;
+  int* d_bin_moved = nullptr;
+  void* d_ent = nullptr;  // fold entries (row within bin, product): 8 (FP32) or 16 (FP64) bytes
 
   // device workspace
   int* d_bp = nullptr;

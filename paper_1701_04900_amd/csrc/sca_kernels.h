@@ -152,21 +152,30 @@ static __global__ void k_init_state(RoundState* st, long long k, double gamma, d
 }
 
 // ------------------------------------------------------------------ S.1: block draw
-// One 1024-thread workgroup.  Each thread owns a contiguous range of blocks; two block
-// scans give every drawn block its rank and its first output position, so the drawn
-// coordinates are listed in ascending order.  When the drawn blocks fit the shared list
-// (kSelList), waves then write each drawn block's coordinates with coalesced stores;
-// otherwise every thread writes its own blocks.  Also advances the round counter and the
-// step of the diminishing rule, and resets the gradient work counter.
+// One 1024-thread workgroup.  The block pointer is first staged in LDS (when it fits), so
+// the draw costs two memory latencies (that load, then the stores).  Each thread owns a
+// contiguous range of blocks; two block scans give every drawn block its rank and its
+// first output position, so the drawn coordinates are listed in ascending order.  When
+// the drawn blocks fit the shared list (kSelList), waves then write each drawn block's
+// coordinates with coalesced stores; otherwise every thread writes its own blocks.  Also
+// advances the round counter and the step of the diminishing rule, and resets the
+// gradient work counter.
 constexpr int kSelList = 4096;
-static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* __restrict__ bp,
-                                                        uint64_t seed, uint32_t inst, uint64_t T,
-                                                        RoundState* __restrict__ st,
-                                                        int* __restrict__ sel_cols) {
-  __shared__ int sh[17];
-  __shared__ int s_blk[kSelList];
-  __shared__ int s_off[kSelList];
+constexpr int kSelBp = 4096;  // block pointers staged in LDS when nblocks < kSelBp
+
+template <typename BP>
+__device__ __forceinline__ void select_run(int nblocks, BP bp, uint64_t seed, uint32_t inst,
+                                           uint64_t T, RoundState* __restrict__ st,
+                                           int* __restrict__ sel_cols, int* sh, int* s_blk,
+                                           int* s_off) {
   const long long k = st->k;
+  double g_next = 0.0, g_mu = 0.0;
+  long long upd = 0;
+  if (threadIdx.x == 0) {  // loaded now so that their latency overlaps the draws
+    g_next = st->gamma_next;
+    g_mu = st->gamma_mu;
+    upd = st->coord_updates;
+  }
   const int per = (nblocks + 1023) / 1024;
   const int b0 = min(nblocks, (int)threadIdx.x * per);
   const int b1 = min(nblocks, b0 + per);
@@ -209,11 +218,27 @@ static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* 
   if (threadIdx.x == 0) {
     st->S_cnt = total;
     st->work_ctr = 0;
-    st->coord_updates += total;
+    st->coord_updates = upd + total;
     st->k = k + 1;
-    const double g = st->gamma_next;
-    st->gamma_cur = g;
-    st->gamma_next = g * (1.0 - st->gamma_mu * g);
+    st->gamma_cur = g_next;
+    st->gamma_next = g_next * (1.0 - g_mu * g_next);
+  }
+}
+
+static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* __restrict__ bp,
+                                                        uint64_t seed, uint32_t inst, uint64_t T,
+                                                        RoundState* __restrict__ st,
+                                                        int* __restrict__ sel_cols) {
+  __shared__ int sh[17];
+  __shared__ int s_blk[kSelList];
+  __shared__ int s_off[kSelList];
+  __shared__ int s_bp[kSelBp];
+  if (nblocks < kSelBp) {
+    for (int i = threadIdx.x; i <= nblocks; i += 1024) s_bp[i] = bp[i];
+    __syncthreads();
+    select_run(nblocks, (const int*)s_bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off);
+  } else {
+    select_run(nblocks, bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off);
   }
 }
 

@@ -66,6 +66,50 @@ def test_sparse_fp64_parity(m, n, per_col, p):
         assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
 
 
+def _irregular(m, n, mean_len, long_len, seed, block=64, p=0.3):
+    """CSR with uneven columns: lengths 1 + Exp(mean_len), every 37th column long_len
+    nonzeros (longer than one pass of the gradient kernel's unrolled loads)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    lens = np.minimum(m, 1 + rng.exponential(mean_len, size=n).astype(np.int64))
+    lens[::37] = long_len
+    rows = np.concatenate([rng.choice(m, L, replace=False) for L in lens])
+    vals = rng.normal(size=rows.size)
+    colptr = np.concatenate([[0], np.cumsum(lens)])
+    for j in range(n):  # unit columns
+        sl = slice(colptr[j], colptr[j + 1])
+        vals[sl] /= np.linalg.norm(vals[sl])
+    A = sp.csc_matrix((vals, rows, colptr), shape=(m, n)).tocsr()
+    A.sort_indices()
+    xt = np.zeros(n)
+    supp = rng.choice(n, max(1, n // 100), replace=False)
+    xt[supp] = rng.uniform(1, 2, supp.size) * rng.choice([-1.0, 1.0], supp.size)
+    b = A @ xt + 0.01 * rng.normal(size=m)
+    lam = 0.02 * float(np.max(np.abs(A.T @ b)))
+    cn = np.asarray(A.multiply(A).sum(axis=0)).ravel()
+    tau = inputs.tau_heuristic(float(cn.min()), float(cn.max()), m, n, p)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt)
+    return inputs.SparseWorkload(f"irregular_{m}x{n}_mean{mean_len}", m, n,
+                                 t(A.indptr, torch.int64), t(A.indices, torch.int32),
+                                 t(A.data, torch.float64), t(b, torch.float64), t(xt, torch.float64),
+                                 lam, 0.0, math.inf, float(tau), inputs.block_partition(n, block),
+                                 p, 0.9, seed, 0)
+
+
+@pytest.mark.parametrize("mean_len,long_len", [(6, 150), (45, 300), (90, 700)])
+def test_sparse_irregular_columns_fp64_parity(mean_len, long_len):
+    w = _irregular(2500, 6000, mean_len, long_len, seed=mean_len)
+    prob = _oracle(w)
+    run = Run(w)
+    for xo, ro in _oracle_traj(w, prob, 30, 5):
+        xg, rg = run.step(5)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+    # a fresh residual at the current point equals the running one to rounding
+    rf = torch.empty_like(run.r)
+    sca.sca_residual(run.P.handle, run.x, rf)
+    assert _rel(rf.cpu().numpy(), O.residual(prob, run.x.cpu().numpy())) <= 1e-13
+
+
 def test_sparse_fp32_objective():
     w = inputs.sparse_lasso_fp32(m=4000, n=40000, per_col=40, seed=2)
     prob = _oracle(w)
