@@ -226,7 +226,8 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
 }
 
 void sca::free_workspace(sca_problem* p) {
-  void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state, p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
+  void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state,
+                  p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
                   p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
                   p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
                   p->csc_colptr, p->csc_rowidx, p->csc_vals, p->d_bin_cnt, p->d_bin_tot,
@@ -422,13 +423,18 @@ extern "C" sca_status sca_profile_get(sca_problem* p, double* ms, int64_t* launc
 }
 
 // ------------------------------------------------------------------ launch sequences
+// S.1: the block draw of the round in flight (see k_select).
+void sca::launch_select(sca_problem* p, const sca_opts* o, uint64_t Tthr, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)p->nblocks, p->d_bp, o->seed,
+                     o->instance, Tthr, p->d_state, p->d_sel_cols);
+}
+
 template <typename T>
 static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
                                uint64_t Tthr, const BRParams& bp) {
   const int m = (int)p->m, n = (int)p->n;
   prof_begin(p, s, SCA_K_SELECT);
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)p->nblocks, p->d_bp, o->seed,
-                     o->instance, Tthr, p->d_state, p->d_sel_cols);
+  launch_select(p, o, Tthr, s);
   prof_end(p, s, 0.0);
   // Algorithmic bytes of the gradient pass: m*sizeof(T) per drawn coordinate (known on
   // the host only in profiling mode, where it is computed from the expected count).

@@ -710,8 +710,7 @@ template <typename T>
 void round_csc(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s, uint64_t Tthr,
                const BRParams& bp) {
   prof_begin(p, s, SCA_K_SELECT);
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)p->nblocks, p->d_bp, o->seed,
-                     o->instance, Tthr, p->d_state, p->d_sel_cols);
+  launch_select(p, o, Tthr, s);
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_GRAD);
   grad_any<T>(p, x, r, bp, s);

@@ -152,14 +152,15 @@ static __global__ void k_init_state(RoundState* st, long long k, double gamma, d
 }
 
 // ------------------------------------------------------------------ S.1: block draw
-// One 1024-thread workgroup.  The block pointer is first staged in LDS (when it fits), so
-// the draw costs two memory latencies (that load, then the stores).  Each thread owns a
-// contiguous range of blocks; two block scans give every drawn block its rank and its
-// first output position, so the drawn coordinates are listed in ascending order.  When
-// the drawn blocks fit the shared list (kSelList), waves then write each drawn block's
-// coordinates with coalesced stores; otherwise every thread writes its own blocks.  Also
-// advances the round counter and the step of the diminishing rule, and resets the
-// gradient work counter.
+// One 1024-thread workgroup.  The block pointer is first staged in LDS (when it fits) and
+// the state fields are loaded at the start, so the draw costs few memory latencies.  Each
+// thread owns a contiguous range of blocks; two block scans give every drawn block its rank
+// and its first output position, so the drawn coordinates are listed in ascending order.
+// When the drawn blocks fit the shared list (kSelList), waves then write each drawn
+// block's coordinates with coalesced stores; otherwise every thread writes its own blocks.
+// Also advances the round counter and the step of the diminishing rule, and resets the
+// gradient work counter.  (A grid of workgroups with a last-arriver listing measured slower
+// here: its device-scope fences cost more than the draws they spread.)
 constexpr int kSelList = 4096;
 constexpr int kSelBp = 4096;  // block pointers staged in LDS when nblocks < kSelBp
 
