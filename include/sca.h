@@ -314,6 +314,69 @@ sca_status sca_batch_objective(sca_batch* batch, const sca_opts* opts, const voi
                                double* F_host, double* merit_host, double* MF_host,
                                int64_t* nnz_host, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Many right-hand sides over one dense A (a sweep over lambda as in the experiments of
+ * Section 4.3, or the perturbed problems of a finite-difference check): K problems
+ *   min 1/2||A x_k - b_k||^2 - c||x_k||^2 + lambda_k ||x_k||_1,  -beta <= x_k <= beta,
+ * k = 0..K-1, solved together with Algorithm 1 under one block draw (the seed and instance
+ * word of the options are shared), so that the partial gradients of a round, A_S^T R, and
+ * its residual update, A_J dX_J, are matrix products run on the matrix cores.  Each
+ * column of X follows, round for round, the iterates the single-problem path produces for
+ * (b_k, lambda_k) with the same options, up to the order of floating-point additions.
+ * The l1 regulariser only.
+ *
+ * Layouts: A as for sca_problem_create_dense (borrowed); B (m x K, column k = b_k, leading
+ * dimension ldb >= m, borrowed); X (n x K, column k = x_k, leading dimension n); R
+ * (m x K, column k = A x_k - b_k, leading dimension lda, 16-byte aligned).  1 <= K <= 64.
+ * --------------------------------------------------------------------------------------- */
+typedef struct sca_multi sca_multi;
+
+/* Create the K-problem set.  lambda_host: K values >= 0.  Errors as for
+ * sca_problem_create_dense, and SCA_EINVAL for K outside [1, 64] or ldb < m.  Synchronises
+ * 'stream'. */
+sca_status sca_multi_create(sca_multi** out, sca_dtype dtype, int64_t m, int64_t n,
+                            const void* A_colmajor_dev, int64_t lda, int64_t K,
+                            const void* B_dev, int64_t ldb, const double* lambda_host,
+                            double c, double beta, const int64_t* block_ptr_host,
+                            int64_t nblocks, void* stream);
+void sca_multi_destroy(sca_multi* mp);
+
+/* F*_k of every problem (K values, nonzero), used by the relative-error stop of
+ * sca_multi_solve. */
+sca_status sca_multi_set_fstar(sca_multi* mp, const double* F_star_host);
+
+/* R = A X - B with FP64 accumulation (rounded once into the dtype).  Stream-ordered. */
+sca_status sca_multi_residual(sca_multi* mp, const void* X_dev, void* R_dev, void* stream);
+
+/* Rounds [round_begin, round_begin + nrounds) of Algorithm 1 on every problem, in place
+ * on X and R (R must hold A X - B on entry).  Stream-ordered; nothing is read back. */
+sca_status sca_multi_step(sca_multi* mp, const sca_opts* opts, int64_t round_begin,
+                          int64_t nrounds, void* X_dev, void* R_dev, void* stream);
+
+/* Per problem (arrays of K, any may be NULL): F_k with a fresh FP64-accumulated residual,
+ * the merit ||xh(x_k) - x_k||_inf (Section 4.3) and nnz(xh(x_k)).  The merit's partial
+ * gradients use FP64 products.  Synchronises 'stream'. */
+sca_status sca_multi_objective(sca_multi* mp, const sca_opts* opts, const void* X_dev,
+                               double* F_host, double* merit_host, int64_t* nnz_host,
+                               void* stream);
+
+/* Solve from X (in: start, out: result) until every problem meets the stop of
+ * sca_solve (relative objective error against its F*, or merit), checked every
+ * check_every rounds; a problem that meets it is frozen (its X column no longer moves)
+ * while the others continue.  stats_host: K entries (struct_size set by the caller).
+ * Returns SCA_ENOTCONV when a problem did not meet its stop within max_rounds.
+ * Synchronises 'stream'. */
+sca_status sca_multi_solve(sca_multi* mp, const sca_opts* opts, void* X_dev,
+                           sca_stats* stats_host, void* stream);
+
+/* Kernel times of the sca_multi_step / sca_multi_solve calls made with SCA_FLAG_PROFILE
+ * (which then launch eagerly, with HIP events around each step), indexed by SCA_K_*
+ * (SCA_K_GRAD: the gradient product; SCA_K_COMPACT: best response and listing of the moved
+ * coordinates; SCA_K_FOLD: the residual-update product and its reduction); arrays of
+ * SCA_K_NKINDS entries.  reset != 0 clears them. */
+sca_status sca_multi_profile_get(sca_multi* mp, double* ms_host, int64_t* launches_host,
+                                 int reset);
+
 #ifdef __cplusplus
 }
 #endif

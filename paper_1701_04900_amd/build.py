@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsca.so")
-SOURCES = ["sca_api.hip", "sca_csc.hip", "sca_batch.hip", "sca_adjoint.hip", "sca_calib.hip"]
+SOURCES = ["sca_api.hip", "sca_csc.hip", "sca_batch.hip", "sca_adjoint.hip", "sca_calib.hip",
+           "sca_multi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -184,6 +184,68 @@ def nonconvex_box_fp32(m=10000, n=50000, seed=0, device="cpu", dtype=torch.float
 
 
 # --------------------------------------------------------------------------------------
+# Many right-hand sides over one dense A
+# --------------------------------------------------------------------------------------
+@dataclass
+class MultiWorkload:
+    name: str
+    At: torch.Tensor          # (n, lda) as for DenseWorkload
+    m: int
+    n: int
+    lda: int
+    B: torch.Tensor           # (K, lda) storage dtype; B[k, :m] = b_k
+    lams: np.ndarray          # (K,) float64
+    c: float
+    beta: float
+    tau: float
+    block_ptr: np.ndarray
+    p: float
+    gamma: float
+    seed: int
+    base: DenseWorkload
+
+    @property
+    def K(self):
+        return int(self.B.shape[0])
+
+    @property
+    def dtype(self):
+        return self.At.dtype
+
+    def b(self, k):
+        return self.B[k, : self.m]
+
+
+def multi_rhs_problem(m: int, n: int, K: int, *, rhs: str = "sweep", lam_range=(0.005, 0.05),
+                      delta: float = 1e-3, nnz_frac: float = 0.01, c_frac: float = 0.0,
+                      beta: float = math.inf, block: int = 64, p: float = 0.25,
+                      gamma: float = 0.9, dtype=torch.float32, seed: int = 0,
+                      device="cpu") -> MultiWorkload:
+    """K problems over the A of ``dense_problem(m, n, ...)``.  rhs="sweep": every b_k is the
+    base b and lam_k = f_k ||A^T b||_inf with f_k log-spaced over lam_range.  rhs="perturbed":
+    b_k = b + delta * u_k with seeded N(0,1) vectors u_k and lam_k = the base lam (the
+    problems of a finite-difference check)."""
+    w = dense_problem(m, n, nnz_frac=nnz_frac, lam_frac=lam_range[0], c_frac=c_frac, beta=beta,
+                      block=block, p=p, gamma=gamma, dtype=dtype, seed=seed, device=device)
+    atb_max = w.lam / lam_range[0]
+    B = torch.zeros(K, w.lda, dtype=dtype, device=device)
+    if rhs == "sweep":
+        f = np.exp(np.linspace(math.log(lam_range[0]), math.log(lam_range[1]), K))
+        lams = f * atb_max
+        B[:, :m] = w.b[None, :]
+    elif rhs == "perturbed":
+        g = _gen(device, seed + 7919)
+        U = torch.randn(K, m, dtype=torch.float64, generator=g, device=device)
+        B[:, :m] = (w.b.double()[None, :] + delta * U).to(dtype)
+        lams = np.full(K, w.lam)
+    else:
+        raise ValueError("rhs must be 'sweep' or 'perturbed'")
+    return MultiWorkload(f"multi_{rhs}_{m}x{n}_K{K}_{str(dtype).split('.')[-1]}", w.At, m, n,
+                         w.lda, B, np.asarray(lams, dtype=np.float64), w.c, w.beta, w.tau,
+                         w.block_ptr, w.p, w.gamma, w.seed, w)
+
+
+# --------------------------------------------------------------------------------------
 # Sparse workloads (CSR)
 # --------------------------------------------------------------------------------------
 @dataclass

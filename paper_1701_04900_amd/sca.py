@@ -118,6 +118,16 @@ SIGNATURES = {
     "sca_batch_objective": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(_D),
                                  ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64),
                                  _P]),
+    "sca_multi_create": (_S, [ctypes.POINTER(_P), _S, _I64, _I64, _P, _I64, _I64, _P, _I64,
+                              ctypes.POINTER(_D), _D, _D, ctypes.POINTER(_I64), _I64, _P]),
+    "sca_multi_destroy": (None, [_P]),
+    "sca_multi_set_fstar": (_S, [_P, ctypes.POINTER(_D)]),
+    "sca_multi_residual": (_S, [_P, _P, _P, _P]),
+    "sca_multi_step": (_S, [_P, ctypes.POINTER(sca_opts), _I64, _I64, _P, _P, _P]),
+    "sca_multi_objective": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(_D),
+                                 ctypes.POINTER(_D), ctypes.POINTER(_I64), _P]),
+    "sca_multi_solve": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(sca_stats), _P]),
+    "sca_multi_profile_get": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), _S]),
 }
 
 _LIB = None
@@ -450,6 +460,97 @@ class Batch:
     def close(self):
         if self.handle is not None:
             sca_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ many right-hand sides
+# Layouts: At (n, lda) as for the dense problem; B (K, ldb), row k = b_k; X (K, n), row k =
+# x_k; R (K, lda), row k = A x_k - b_k (rows m..lda-1 unused).
+def sca_multi_create(At, m, B, lams, c=0.0, beta=math.inf, block_ptr=None, stream=None):
+    n, lda = At.shape
+    K, ldb = B.shape
+    if block_ptr is None:
+        block_ptr = np.arange(n + 1, dtype=np.int64)
+    bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
+    la = np.ascontiguousarray(lams, dtype=np.float64)
+    if la.shape != (K,):
+        raise ValueError("one lambda per right-hand side")
+    h = ctypes.c_void_p()
+    _check(lib().sca_multi_create(ctypes.byref(h), _dtype_code(At.dtype), m, n, _dptr(At), lda,
+                                  K, _dptr(B), ldb, la.ctypes.data_as(ctypes.POINTER(_D)),
+                                  float(c), float(beta), bp.ctypes.data_as(ctypes.POINTER(_I64)),
+                                  len(bp) - 1, _stream(stream)))
+    return h
+
+
+def sca_multi_destroy(h):
+    lib().sca_multi_destroy(h)
+
+
+def sca_multi_set_fstar(h, F_star):
+    a = np.ascontiguousarray(F_star, dtype=np.float64)
+    _check(lib().sca_multi_set_fstar(h, a.ctypes.data_as(ctypes.POINTER(_D))))
+
+
+def sca_multi_residual(h, X, R, stream=None):
+    _check(lib().sca_multi_residual(h, _dptr(X), _dptr(R), _stream(stream)))
+
+
+def sca_multi_step(h, opts, round_begin, nrounds, X, R, stream=None):
+    _check(lib().sca_multi_step(h, ctypes.byref(opts), round_begin, nrounds, _dptr(X), _dptr(R),
+                                _stream(stream)))
+
+
+def sca_multi_objective(h, opts, X, K, stream=None):
+    F, mer, nnz = (_D * K)(), (_D * K)(), (_I64 * K)()
+    _check(lib().sca_multi_objective(h, ctypes.byref(opts), _dptr(X), F, mer, nnz,
+                                     _stream(stream)))
+    return dict(F=np.array(F[:]), merit=np.array(mer[:]), nnz=np.array(nnz[:]))
+
+
+def sca_multi_solve(h, opts, X, K, stream=None, raise_on_notconv=True):
+    st = (sca_stats * K)()
+    for k in range(K):
+        st[k].struct_size = ctypes.sizeof(sca_stats)
+    status = lib().sca_multi_solve(h, ctypes.byref(opts), _dptr(X), st, _stream(stream))
+    if status != SCA_OK and not (status == SCA_ENOTCONV and not raise_on_notconv):
+        _check(status)
+    return [st[k].as_dict() for k in range(K)]
+
+
+def sca_multi_profile_get(h, reset=False):
+    ms = (_D * SCA_K_NKINDS)()
+    n = (_I64 * SCA_K_NKINDS)()
+    _check(lib().sca_multi_profile_get(h, ms, n, int(reset)))
+    names = ["select", "grad", "compact", "fold"]
+    return {names[k]: dict(ms=ms[k], launches=n[k]) for k in range(SCA_K_NKINDS)}
+
+
+class Multi:
+    """K right-hand sides over one dense A (borrowed device tensors kept alive)."""
+
+    def __init__(self, At, m, B, lams, c=0.0, beta=math.inf, block_ptr=None, stream=None):
+        self.K, self.m, self.n = B.shape[0], m, At.shape[0]
+        self.lda = At.shape[1]
+        self.dtype = At.dtype
+        self._keep = (At, B)
+        self.handle = sca_multi_create(At, m, B, lams, c, beta, block_ptr, stream)
+
+    def zeros_x(self):
+        return torch.zeros(self.K, self.n, dtype=self.dtype, device="cuda")
+
+    def empty_r(self):
+        return torch.zeros(self.K, self.lda, dtype=self.dtype, device="cuda")
+
+    def close(self):
+        if self.handle is not None:
+            sca_multi_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
