@@ -197,6 +197,129 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def bench_multi(args):
+    """A sweep of K lambda values over the 20000 x 100000 FP32 LASSO (same A and b, lam_k =
+    f_k ||A^T b||_inf with f_k log-spaced over [0.005, 0.05]): one multi-right-hand-side solve
+    of all K problems to relative error 1e-6 each (gradients and residual updates as MFMA
+    products) against the same K problems solved one after another by the single-problem
+    path."""
+    K = args.rhs
+    t0 = time.perf_counter()
+    w = inputs.multi_rhs_problem(args.m, args.n, K, rhs="sweep", lam_range=(0.005, 0.05),
+                                 nnz_frac=0.01, block=64, p=0.25, dtype=torch.float32, seed=0,
+                                 device="cuda")
+    torch.cuda.synchronize()
+    log(f"generated {w.name} in {time.perf_counter() - t0:.1f} s: tau={w.tau:.4g}")
+    okw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+    # F*_k: an FP64 multi solve of the stored data (upcast copies) to merit <= 1e-12
+    t0 = time.perf_counter()
+    At64, B64 = w.At.double(), w.B.double()
+    M64 = sca.Multi(At64, w.m, B64, w.lams, w.c, w.beta, w.block_ptr)
+    X64 = M64.zeros_x()
+    st64 = sca.sca_multi_solve(M64.handle, sca.make_opts(**okw, max_rounds=200000,
+                                                         check_every=50, tol_merit=1e-12),
+                               X64, K, raise_on_notconv=False)
+    F_star = [s["F"] for s in st64]
+    log(f"F* of {K} problems in {time.perf_counter() - t0:.1f} s: max rounds "
+        f"{max(s['rounds'] for s in st64)}, max merit {max(s['merit'] for s in st64):.1e}")
+    M64.close()
+    del M64, At64, B64, X64
+    torch.cuda.empty_cache()
+    M = sca.Multi(w.At, w.m, w.B, w.lams, w.c, w.beta, w.block_ptr)
+    sca.sca_multi_set_fstar(M.handle, F_star)
+    opts = sca.make_opts(**okw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol)
+    X = M.zeros_x()
+    for _ in range(args.warmup):
+        X.zero_()
+        sca.sca_multi_solve(M.handle, opts, X, K)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        X.zero_()
+        stats.append(sca.sca_multi_solve(M.handle, opts, X, K))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    upd = sum(s["coord_updates"] for st in stats for s in st)
+    rounds = max(s["rounds"] for s in stats[-1])
+    log(f"multi solve: {elapsed / args.steps * 1e3:.1f} ms, {rounds} rounds, max rel err "
+        f"{max(s['rel_err'] for s in stats[-1]):.2e}")
+    roof, prof_pass = None, None
+    if not args.no_profile:
+        popts = sca.make_opts(**okw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
+                              flags=sca.SCA_FLAG_PROFILE)
+        sca.sca_multi_profile_get(M.handle, reset=True)
+        pst = []
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(args.steps):
+            X.zero_()
+            pst.append(sca.sca_multi_solve(M.handle, popts, X, K))
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - tp
+        prof = sca.sca_multi_profile_get(M.handle, reset=True)
+        # algorithmic flops of the gradient product: 2 m K per drawn coordinate (every drawn
+        # coordinate is evaluated for all K problems, frozen ones included)
+        drawn = sum(max(s["coord_updates"] for s in st) for st in pst)
+        moved = sum(st[0]["moved_updates"] for st in pst)
+        g, f = prof["grad"], prof["fold"]
+        gflop = 2.0 * w.m * K * drawn
+        ffl = 2.0 * w.m * K * moved
+        achieved = gflop / (g["ms"] * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 2), peak=MFMA_FP32_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
+                    traffic=None, kernel="k_mgrad<float,float,4>",
+                    avg_launch_ms=round(g["ms"] / g["launches"], 4),
+                    alg_flop_per_launch=round(gflop / g["launches"]))
+        prof_pass = dict(ms_per_step=pel / args.steps * 1e3,
+                         per_launch_ms={k: round(v["ms"] / max(1, v["launches"]), 4)
+                                        for k, v in prof.items()},
+                         fold_TFLOPs=round(ffl / (f["ms"] * 1e-3) / 1e12, 2) if f["ms"] else None)
+        log(f"profiled pass: {prof_pass}, roofline {roof}")
+    # the same K problems, one single-problem solve after another
+    plain_t, plain_upd = 0.0, 0
+    probs = [sca.Problem.dense(w.At, w.m, w.B[k, : w.m], float(w.lams[k]), w.c, w.beta,
+                               w.block_ptr) for k in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, P in enumerate(probs):
+        ok = sca.make_opts(**okw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
+                           F_star=F_star[k])
+        xk = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+        plain_upd += sca.sca_solve(P.handle, ok, xk)["coord_updates"]
+    torch.cuda.synchronize()
+    plain_t = time.perf_counter() - t0
+    log(f"single-problem solves one after another: {plain_t * 1e3:.1f} ms")
+    cpu = None
+    if not args.no_cpu_baseline:
+        w1 = inputs.DenseWorkload(w.name, w.At, w.m, w.n, w.lda, w.B[K // 2, : w.m],
+                                  w.base.x_true, float(w.lams[K // 2]), w.c, w.beta, w.tau,
+                                  w.block_ptr, w.p, w.gamma, w.seed)
+        cpu = cpu_baseline(w1, okw, args.cpu_rounds or 12)
+        cpu["sample"] = cpu["sample"] + f" (problem {K // 2} of the sweep, lam={w.lams[K // 2]:.4g})"
+        log(f"cpu baseline: {cpu}")
+    out = {
+        "metric": METRIC, "value": upd / elapsed, "unit": "coord-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"multi_rhs_lasso_{w.m}x{w.n}_K{K}_lambda_sweep_fp32",
+                   "m": w.m, "n": w.n, "K": K, "lam_frac_range": [0.005, 0.05], "block": 64,
+                   "select_p": w.p, "gamma": w.gamma, "tol_rel_obj": args.tol,
+                   "step": "one multi solve of all K problems from X=0"},
+        "max_rel_err": max(s["rel_err"] for s in stats[-1]),
+        "rounds_to_all": rounds,
+        "plain_sequential": {"time_to_all_tol_s": plain_t,
+                             "coord_updates_per_s": plain_upd / plain_t},
+        "multi_speedup": plain_t / (elapsed / args.steps),
+        "roofline": roof, "profiled_pass": prof_pass, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_grad_br_wg_lasso_20000x100000_fp32.txt")
 CALIB_BYTES = 1 << 30
 
@@ -317,8 +440,9 @@ def main():
                     help="rounds per step of the box-nonconvex workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["lasso", "nonconvex", "sparse", "batch"],
+    ap.add_argument("--workload", choices=["lasso", "nonconvex", "sparse", "batch", "multi"],
                     default="lasso")
+    ap.add_argument("--rhs", type=int, default=64, help="right-hand sides of --workload multi")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_JSON"))
@@ -337,6 +461,9 @@ def main():
     sca.lib()
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "multi":
+        bench_multi(args)
         return
     if args.pmc_probe:
         pmc_probe(args)

@@ -363,8 +363,10 @@ sca_status sca_multi_objective(sca_multi* mp, const sca_opts* opts, const void* 
 /* Solve from X (in: start, out: result) until every problem meets the stop of
  * sca_solve (relative objective error against its F*, or merit), checked every
  * check_every rounds; a problem that meets it is frozen (its X column no longer moves)
- * while the others continue.  stats_host: K entries (struct_size set by the caller).
- * Returns SCA_ENOTCONV when a problem did not meet its stop within max_rounds.
+ * while the others continue.  stats_host: K entries (struct_size set by the caller);
+ * coord_updates counts the drawn coordinates of the rounds in which that problem was
+ * active, moved_updates the coordinates moved in any problem (shared), MF is not computed
+ * (NaN).  Returns SCA_ENOTCONV when a problem did not meet its stop within max_rounds.
  * Synchronises 'stream'. */
 sca_status sca_multi_solve(sca_multi* mp, const sca_opts* opts, void* X_dev,
                            sca_stats* stats_host, void* stream);

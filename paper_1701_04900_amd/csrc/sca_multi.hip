@@ -49,6 +49,7 @@ struct sca_multi {
   void* d_Xt = nullptr;      // X rows (n x KP, FP64 room) for fresh residuals
   int* d_active = nullptr;   // per problem: 1 while it still moves
   long long* d_done = nullptr;  // round at which a problem met its stop (-1: not yet)
+  long long* d_upd = nullptr;   // per problem: coordinate updates while it was active
   double* d_F = nullptr;     // per problem F (K)
   double* d_mer = nullptr;   // per problem merit (K)
   int* d_nnz = nullptr;      // per problem nnz(xh) (K)
@@ -224,17 +225,19 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
 
 // Best response and relaxed step of every (drawn coordinate t, problem j): one wave per t,
 // lane j.  g = sum of the kMNS partials (fixed order) - 2c x; a frozen problem does not move.
-// D[t][j] = the move; mv[t] = 1 when any problem moved coordinate t.
+// D[t][j] = the move; mv[t] = 1 when any problem moved coordinate t; upd[j] += S for the
+// problems still active.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_mbr(const T* __restrict__ G, long long ldg, const int* __restrict__ list,
       const int* __restrict__ S_ptr, T* __restrict__ X, long long ldx,
       const double* __restrict__ cn2, const double* __restrict__ lam,
       const int* __restrict__ active, const RoundState* __restrict__ st, BRParams bp, int K,
-      int KP, T* __restrict__ D, T* __restrict__ mv) {
+      int KP, T* __restrict__ D, T* __restrict__ mv, long long* __restrict__ upd) {
   const int lane = threadIdx.x & 63;
   const int S = *S_ptr;
   const T gamma = (T)st->gamma_cur;
+  if (blockIdx.x == 0 && threadIdx.x < K && active[threadIdx.x]) upd[threadIdx.x] += S;
   for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < S; t += gridDim.x * 4) {
     const int col = list[t];
     T d = (T)0;
@@ -491,11 +494,13 @@ __global__ void k_mneg(const void* __restrict__ Bv, long long ldb, int m, int K,
   }
 }
 
-__global__ void k_minit(int K, int* __restrict__ active, long long* __restrict__ done) {
+__global__ void k_minit(int K, int* __restrict__ active, long long* __restrict__ done,
+                        long long* __restrict__ upd) {
   const int j = threadIdx.x;
   if (j < K) {
     active[j] = 1;
     done[j] = -1;
+    upd[j] = 0;
   }
 }
 
@@ -636,7 +641,7 @@ void mround(sca_multi* M, const sca_opts* o, T* X, T* R, hipStream_t s, uint64_t
   hipLaunchKernelGGL(k_mbr<T>, dim3(bgrid), dim3(256), 0, s, (const T*)M->d_G, ldg_of(M),
                      (const int*)M->d_sel, (const int*)S_ptr, X, (long long)M->n, M->d_cn2,
                      M->d_lam, (const int*)M->d_active, (const RoundState*)M->d_state, bp, K, KP,
-                     (T*)M->d_D, (T*)M->d_mv);
+                     (T*)M->d_D, (T*)M->d_mv, M->d_upd);
   mcompact<T>(M, (const T*)M->d_mv, S_ptr, 1, s);
   mprof_end(M, s);
   mprof_begin(M, s, SCA_K_FOLD);
@@ -724,7 +729,8 @@ void mfree(sca_multi* M) {
   void* ptrs[] = {M->d_bp,  M->d_cn2,    M->d_lam,  M->d_fstar, M->d_state, M->d_sel,
                   M->d_iota, M->d_nall,  M->d_G,    M->d_D,     M->d_mv,    M->d_chunk,
                   M->d_J,   M->d_Jv,     M->d_Rp,   M->d_R,     M->d_R64,   M->d_Xt,
-                  M->d_active, M->d_done, M->d_F,   M->d_mer,   M->d_nnz,   M->d_part};
+                  M->d_active, M->d_done, M->d_F,   M->d_mer,   M->d_nnz,   M->d_part,
+                  M->d_upd};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (M->graph) (void)hipGraphExecDestroy(M->graph);
@@ -809,6 +815,7 @@ extern "C" sca_status sca_multi_create(sca_multi** out, sca_dtype dtype, int64_t
   MALLOC(M->d_Xt, sizeof(double) * (size_t)n * KP);
   MALLOC(M->d_active, sizeof(int) * kMaxK);
   MALLOC(M->d_done, sizeof(long long) * kMaxK);
+  MALLOC(M->d_upd, sizeof(long long) * kMaxK);
   MALLOC(M->d_F, sizeof(double) * kMaxK);
   MALLOC(M->d_mer, sizeof(double) * kMaxK);
   MALLOC(M->d_nnz, sizeof(int) * kMaxK);
@@ -828,7 +835,8 @@ extern "C" sca_status sca_multi_create(sca_multi** out, sca_dtype dtype, int64_t
   hipLaunchKernelGGL(k_miota, dim3(256), dim3(256), 0, s, M->d_iota, (int)n);
   hipLaunchKernelGGL(k_mset_one, dim3(1), dim3(1), 0, s, M->d_nall, (int)n);
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, M->d_state, 0ll, 1.0, 0.0, (int)n, 1);
-  hipLaunchKernelGGL(k_minit, dim3(1), dim3(64), 0, s, (int)K, M->d_active, M->d_done);
+  hipLaunchKernelGGL(k_minit, dim3(1), dim3(64), 0, s, (int)K, M->d_active, M->d_done,
+                     M->d_upd);
   if (dtype == SCA_F32)
     hipLaunchKernelGGL(k_colnorm2<float>, dim3(4 * M->ncu), dim3(256), 0, s, (const float*)A,
                        (long long)lda, (int)m, (int)n, M->d_cn2);
@@ -900,7 +908,8 @@ extern "C" sca_status sca_multi_step(sca_multi* M, const sca_opts* o, int64_t ro
   const double g = gamma_at_round(o->gamma, o->gamma_mu, round_begin);
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, M->d_state, (long long)round_begin, g,
                      o->gamma_mu, (int)M->n, 1);
-  hipLaunchKernelGGL(k_minit, dim3(1), dim3(64), 0, s, (int)M->K, M->d_active, M->d_done);
+  hipLaunchKernelGGL(k_minit, dim3(1), dim3(64), 0, s, (int)M->K, M->d_active, M->d_done,
+                     M->d_upd);
   for (int64_t q = 0; q < nrounds; ++q) {
     if (M->dtype == SCA_F32)
       mround<float>(M, o, (float*)X, (float*)R, s, Tthr, bp);
@@ -996,7 +1005,8 @@ extern "C" sca_status sca_multi_solve(sca_multi* M, const sca_opts* o, void* X,
   void* R = M->d_R;
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, M->d_state, 0ll,
                      gamma_at_round(o->gamma, o->gamma_mu, 0), o->gamma_mu, (int)M->n, 1);
-  hipLaunchKernelGGL(k_minit, dim3(1), dim3(64), 0, s, (int)M->K, M->d_active, M->d_done);
+  hipLaunchKernelGGL(k_minit, dim3(1), dim3(64), 0, s, (int)M->K, M->d_active, M->d_done,
+                     M->d_upd);
   if (M->dtype == SCA_F32)
     mresidual<float>(M, (const float*)X, (float*)R, s);
   else
@@ -1060,9 +1070,11 @@ extern "C" sca_status sca_multi_solve(sca_multi* M, const sca_opts* o, void* X,
   std::vector<double> F(M->K), mer(M->K);
   std::vector<int64_t> nnz(M->K);
   if ((st = mreport(M, o, X, F.data(), mer.data(), nnz.data(), s)) != SCA_OK) return st;
-  std::vector<long long> done(M->K);
+  std::vector<long long> done(M->K), pupd(M->K);
   long long upd[2] = {0, 0};
   if (hipMemcpy(done.data(), M->d_done, sizeof(long long) * M->K, hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(pupd.data(), M->d_upd, sizeof(long long) * M->K, hipMemcpyDeviceToHost) !=
           hipSuccess ||
       hipMemcpy(upd, (char*)M->d_state + offsetof(RoundState, coord_updates),
                 sizeof(long long) * 2, hipMemcpyDeviceToHost) != hipSuccess)
@@ -1078,8 +1090,8 @@ extern "C" sca_status sca_multi_solve(sca_multi* M, const sca_opts* o, void* X,
     if (stats) {
       sca_stats& S = stats[q];
       S.rounds = done[q] >= 0 ? done[q] : k;
-      S.coord_updates = upd[0];  // drawn coordinates, shared by the problems
-      S.moved_updates = upd[1];  // coordinates moved in any problem
+      S.coord_updates = pupd[q];  // drawn coordinates while this problem was active
+      S.moved_updates = upd[1];   // coordinates moved in any problem (shared)
       S.F = F[q];
       S.merit = mer[q];
       S.MF = NAN;
