@@ -72,10 +72,10 @@ namespace {
 
 constexpr int kMTC = 128;  // gradient tile: drawn coordinates per workgroup
 constexpr int kMKC = 32;   // gradient: rows of R staged per LDS chunk
-constexpr int kMNS = 4;    // gradient: row splits (partials reduced in the best response)
-constexpr int kMFR = 128;  // fold tile: rows per workgroup
+constexpr int kMNS = 8;    // gradient: row splits (partials reduced in the best response)
+constexpr int kMFR = 256;  // fold tile: rows per workgroup (64 per wave)
 constexpr int kMEC = 32;   // fold: list entries staged per LDS chunk
-constexpr int kMFS = 4;    // fold: list splits (partials reduced in the fold reduction)
+constexpr int kMFS = 8;    // fold: list splits (partials reduced in the fold reduction)
 constexpr int kMaxK = 64;
 
 // 16x16x4 MFMA: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k; element (i, j) of
@@ -136,7 +136,8 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
         long long ldg) {
   typedef Mma<TM> M;
   constexpr int KP = NST * 16;
-  __shared__ TM s_r[KP][kMKC + 1];
+  constexpr int LD = kMKC + 4;  // LDS row stride (keeps every quad 16-byte aligned)
+  __shared__ TM s_r[KP][LD];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int S = *S_ptr;
   const int sp = blockIdx.y;
@@ -157,8 +158,31 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
 #pragma unroll
       for (int s = 0; s < NST; ++s) acc[c][s] = (typename M::acc){0, 0, 0, 0};
     for (int r0 = rlo; r0 < rhi; r0 += kMKC) {
+      // this lane's A quads of the chunk (issued before the R copy so the latencies overlap)
+      Quad<TM> a[kMKC / 16][2];
+#pragma unroll
+      for (int step = 0; step < kMKC / 16; ++step) {
+        const int rb = r0 + 16 * step + 4 * kq;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[step][c].v[u] = (TM)0;
+          if (col[c] >= 0) {
+            const TA* p = A + (size_t)col[c] * lda + rb;
+            if (rb + 3 < rhi) {
+              const Quad<TA> qa = load_quad<TA>(p);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) a[step][c].v[u] = (TM)qa.v[u];
+            } else {
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (rb + u < rhi) a[step][c].v[u] = (TM)p[u];
+            }
+          }
+        }
+      }
       __syncthreads();
-      // R rows r0..r0+kMKC-1 of every problem into LDS (zeros past m and past K)
+      // R rows r0..r0+kMKC-1 of every problem into LDS (zeros past the split and past K)
       for (int q = threadIdx.x; q < KP * (kMKC / 4); q += 256) {
         const int j = q / (kMKC / 4), rr = 4 * (q % (kMKC / 4));
         Quad<TM> v;
@@ -180,34 +204,15 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
       __syncthreads();
 #pragma unroll
       for (int step = 0; step < kMKC / 16; ++step) {
-        const int rb = r0 + 16 * step + 4 * kq;  // this lane's four rows
-        Quad<TM> a[2];
+        Quad<TM> bq[NST];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int s = 0; s < NST; ++s) bq[s] = load_quad<TM>(&s_r[16 * s + li][16 * step + 4 * kq]);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a[c].v[u] = (TM)0;
-          if (col[c] >= 0) {
-            const TA* p = A + (size_t)col[c] * lda + rb;
-            if (rb + 3 < rhi) {
-              const Quad<TA> qa = load_quad<TA>(p);
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-              for (int u = 0; u < 4; ++u) a[c].v[u] = (TM)qa.v[u];
-            } else {
+          for (int s = 0; s < NST; ++s)
 #pragma unroll
-              for (int u = 0; u < 4; ++u)
-                if (rb + u < rhi) a[c].v[u] = (TM)p[u];
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-#pragma unroll
-          for (int s = 0; s < NST; ++s) {
-            const TM b = s_r[16 * s + li][16 * step + 4 * kq + u];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) acc[c][s] = M::mma(a[c].v[u], b, acc[c][s]);
-          }
-        }
+            for (int c = 0; c < 2; ++c) acc[c][s] = M::mma(a[step][c].v[u], bq[s].v[u], acc[c][s]);
       }
     }
     // partials of this tile
@@ -312,9 +317,12 @@ __global__ void k_mprobe_final(const double* __restrict__ pmax, const int* __res
 
 // Fold partials P[sp][r][j] = sum over list entries e of split sp (ascending) of
 // A[r][col(e)] * D[t(e)][j], t(e) = J[e], col(e) = colmap ? colmap[t(e)] : t(e).
-// Workgroup tile: kMFR rows x KP problems; wave w takes rows 32w..32w+31 of the tile (two
-// MFMA tiles) against all KP problems.  Entries are staged kMEC at a time: their rows of
-// D in LDS, their columns in LDS; each lane reads A[r][col] for its row and K slot.
+// Workgroup tile: kMFR rows x KP problems; wave w takes rows 64w..64w+63 of the tile.  Lane
+// (i, k) of an MFMA reads the 16-byte quad of rows 4i..4i+3 (of the wave's 64) of entry
+// k's column and feeds component u to MFMA u, whose result rows are 4i + u: four MFMAs per
+// problem tile cover the 64 rows.  Entries are staged kMEC at a time (their rows of D in
+// LDS); the chunk's A quads are issued before the staging.  (Loading the next chunk into
+// registers during the current one measured slower: it halves the waves per SIMD.)
 template <typename TA, typename TD, typename TM, int NST>
 __global__ void __launch_bounds__(256)
 k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D,
@@ -323,57 +331,66 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
   typedef Mma<TM> M;
   constexpr int KP = NST * 16;
   __shared__ TM s_d[kMEC][KP + 1];
-  __shared__ int s_col[kMEC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, li = lane & 15;
   const int Jn = st->J_cnt;
   const int sp = blockIdx.y;
   const int per = ((Jn + kMFS - 1) / kMFS + 3) / 4 * 4;
   const int elo = min(Jn, sp * per), ehi = min(Jn, elo + per);
-  const int rb = blockIdx.x * kMFR + 32 * wave;
-  typename M::acc acc[2][NST];
+  const int rb = blockIdx.x * kMFR + 64 * wave + 4 * li;  // this lane's four rows
+  typename M::acc acc[4][NST];
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int s = 0; s < NST; ++s) acc[c][s] = (typename M::acc){0, 0, 0, 0};
+    for (int s = 0; s < NST; ++s) acc[u][s] = (typename M::acc){0, 0, 0, 0};
   for (int e0 = elo; e0 < ehi; e0 += kMEC) {
+    Quad<TM> a[kMEC / 4];
+#pragma unroll
+    for (int step = 0; step < kMEC / 4; ++step) {
+      const int e = e0 + 4 * step + kq;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[step].v[u] = (TM)0;
+      if (e < ehi && rb < m) {
+        const int col = colmap ? colmap[J[e]] : J[e];
+        const TA* p = A + (size_t)col * lda + rb;
+        if (rb + 3 < m) {
+          const Quad<TA> qa = load_quad<TA>(p);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[step].v[u] = (TM)qa.v[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (rb + u < m) a[step].v[u] = (TM)p[u];
+        }
+      }
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < kMEC * KP; q += 256) {
       const int ee = q / KP, j = q % KP;
       const int e = e0 + ee;
       s_d[ee][j] = e < ehi ? (TM)D[(size_t)J[e] * KP + j] : (TM)0;
     }
-    if (threadIdx.x < kMEC) {
-      const int e = e0 + threadIdx.x;
-      s_col[threadIdx.x] = e < ehi ? (colmap ? colmap[J[e]] : J[e]) : -1;
-    }
     __syncthreads();
 #pragma unroll
     for (int step = 0; step < kMEC / 4; ++step) {
       const int ee = 4 * step + kq;
-      const int col = s_col[ee];
-      TM a[2];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int r = rb + 16 * c + li;
-        a[c] = (col >= 0 && r < m) ? (TM)A[(size_t)col * lda + r] : (TM)0;
-      }
 #pragma unroll
       for (int s = 0; s < NST; ++s) {
         const TM b = s_d[ee][16 * s + li];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[c][s] = M::mma(a[c], b, acc[c][s]);
+        for (int u = 0; u < 4; ++u) acc[u][s] = M::mma(a[step].v[u], b, acc[u][s]);
       }
     }
   }
+  const int wr = blockIdx.x * kMFR + 64 * wave;
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int s = 0; s < NST; ++s)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int r = rb + 16 * c + M::row(lane, g);
-        if (r < m) P[(size_t)sp * ldp + (size_t)r * KP + 16 * s + li] = acc[c][s][g];
+        const int r = wr + 4 * M::row(lane, g) + u;
+        if (r < m) P[(size_t)sp * ldp + (size_t)r * KP + 16 * s + li] = acc[u][s][g];
       }
 }
 
