@@ -138,3 +138,37 @@ def test_batch_256_full_size_sampled_instances():
         Fo = O.objective(prob, xo, ro)
         assert abs(Fg_all[k] - Fo) <= 1e-4 * abs(Fo), k
     B.close()
+
+
+def test_multi_rhs_20000x100000_K64_fp32_full_size():
+    print("[gpu] full-size multi right-hand sides: 64 lambdas over the 20000x100000 FP32 LASSO",
+          flush=True)
+    w = inputs.multi_rhs_problem(20000, 100000, 64, rhs="sweep", lam_range=(0.005, 0.05),
+                                 nnz_frac=0.01, block=64, p=0.25, dtype=torch.float32, seed=0,
+                                 device="cuda")
+    M = sca.Multi(w.At, w.m, w.B, w.lams, w.c, w.beta, w.block_ptr)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+    X = M.zeros_x()
+    R = M.empty_r()
+    sca.sca_multi_residual(M.handle, X, R)
+    sca.sca_multi_step(M.handle, o, 0, 1, X, R)
+    X1 = X.double().cpu().numpy()
+    sca.sca_multi_step(M.handle, o, 1, 1, X, R)
+    F2 = sca.sca_multi_objective(M.handle, o, X, w.K)["F"]
+    X2 = X.double().cpu().numpy()
+    A32 = w.At.cpu()[:, : w.m].numpy().T
+    for k in (0, 32, 63):
+        wk = inputs.DenseWorkload(w.name, w.At, w.m, w.n, w.lda, w.B[k, : w.m], w.base.x_true,
+                                  float(w.lams[k]), w.c, w.beta, w.tau, w.block_ptr, w.p,
+                                  w.gamma, w.seed)
+        prob = O.Problem(A=A32, b=w.B[k, : w.m].double().cpu().numpy(), lam=float(w.lams[k]),
+                         block_ptr=w.block_ptr)
+        _first_round_one_by_one(wk, prob, X1[k], nsample=1000)
+        cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
+        x, r, _ = O.run_rounds(prob, cfg, np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0, 2)
+        assert _rel(X2[k], x) <= 1e-3, k
+        Fo = O.objective(prob, x, r)
+        assert abs(F2[k] - Fo) <= 1e-4 * abs(Fo), (k, F2[k], Fo)
+        print(f"[parity] multi full-size problem {k}: x err {_rel(X2[k], x):.2e}, "
+              f"F rel err {abs(F2[k] - Fo) / abs(Fo):.2e}", flush=True)
+    M.close()
