@@ -273,6 +273,41 @@ def sca_round(prob: Problem, x, r, tau, gamma, idx):
     return x_new, r_new, int(moved.sum())
 
 
+def sca_round_delayed(prob: Problem, x, r, tau, gamma, idx, chunks: int, stale: int):
+    """One round with bounded delays (Algorithm 1 with delayed iterates x~ = x^(k-d), the
+    delays bounded as in Assumption D1): the drawn coordinates idx (ascending) are updated
+    in `chunks` consecutive groups of ceil(len(idx)/chunks); group t reads the residual
+    left by groups 0 .. t-1-stale of the round, so every coordinate it updates sees all
+    moves older than `stale` groups and none of the newer ones (delays below
+    (stale + 1) * group size), while its own coordinate is current (Assumption D4: each
+    coordinate is drawn once per round).  chunks <= 1 or stale >= chunks - 1 is the round of
+    sca_round; stale = 0 with one coordinate per group is sequential coordinate descent.
+    Returns (x_new, r_new, number of coordinates whose value changed)."""
+    x = np.asarray(x, dtype=np.float64).copy()
+    r0 = np.asarray(r, dtype=np.float64).copy()
+    S = len(idx)
+    if S == 0:
+        return x, r0, 0
+    q = max(1, int(chunks))
+    per = -(-S // q)
+    versions = [r0]  # versions[t] = residual after groups 0 .. t-1
+    moved_total = 0
+    for t in range(q):
+        sub = idx[min(S, t * per):min(S, t * per + per)]
+        r_read = versions[max(0, t - stale)]
+        if len(sub):
+            xhat = best_response(prob, x, r_read, sub, tau)
+            dx = gamma * (xhat - x[sub])
+            x[sub] = x[sub] + dx
+            moved = dx != 0.0
+            moved_total += int(moved.sum())
+            r_next = versions[-1] + (prob.Av(dx[moved], sub[moved]) if moved.any() else 0.0)
+        else:
+            r_next = versions[-1].copy()
+        versions.append(np.asarray(r_next, dtype=np.float64))
+    return x, versions[-1], moved_total
+
+
 def objective(prob: Problem, x, r=None) -> float:
     """F(x) = 1/2||r||^2 - c||x||^2 + lam * sum h(x_j) with r = Ax - b."""
     x = np.asarray(x, dtype=np.float64)
@@ -318,6 +353,8 @@ class RunConfig:
     p: float = 1.0
     seed: int = 0
     instance: int = 0
+    delay_chunks: int = 0      # > 1: rounds of sca_round_delayed
+    delay_stale: int = 0
 
 
 def run_rounds(prob: Problem, cfg: RunConfig, x, r, k0: int, nrounds: int, trace=None):
@@ -332,7 +369,11 @@ def run_rounds(prob: Problem, cfg: RunConfig, x, r, k0: int, nrounds: int, trace
     for k in range(k0, k0 + nrounds):
         mask = selected_blocks(cfg.seed, k, cfg.instance, nblocks, cfg.p)
         idx = block_columns(bp, mask)
-        x, r, _ = sca_round(prob, x, r, cfg.tau, gamma, idx)
+        if cfg.delay_chunks > 1:
+            x, r, _ = sca_round_delayed(prob, x, r, cfg.tau, gamma, idx, cfg.delay_chunks,
+                                        cfg.delay_stale)
+        else:
+            x, r, _ = sca_round(prob, x, r, cfg.tau, gamma, idx)
         updates += len(idx)
         if trace is not None:
             trace.append((k, x.copy(), r.copy()))

@@ -435,3 +435,96 @@ def test_adjoint_nonconvex_c_matches_finite_differences():
                               block_ptr=prob.block_ptr)
     fd = (solve(mk(prob.b + h * u)) - solve(mk(prob.b - h * u))) / (2 * h)
     np.testing.assert_allclose(O.adjoint_jvp(prob, xs, u, 0.0, tau), fd, atol=1e-8)
+
+
+# --------------------------------------------------------------------------------------
+# Bounded-delay rounds (delayed iterates x~ = x^(k-d), Assumption D1)
+# --------------------------------------------------------------------------------------
+def _small_problem(seed, m=30, n=40, c=0.0, beta=math.inf, lam_frac=0.1, block=5):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(m, n))
+    A /= np.linalg.norm(A, axis=0)
+    xt = np.zeros(n)
+    xt[rng.choice(n, 6, replace=False)] = rng.uniform(1, 2, 6) * rng.choice([-1, 1], 6)
+    b = A @ xt + 0.01 * rng.normal(size=m)
+    lam = lam_frac * np.max(np.abs(A.T @ b))
+    return O.Problem(A=A, b=b, lam=lam, c=c, beta=beta,
+                     block_ptr=np.arange(0, n + 1, block) if n % block == 0 else
+                     np.append(np.arange(0, n, block), n))
+
+
+@pytest.mark.parametrize("chunks,stale", [(1, 0), (4, 3), (5, 9)])
+def test_delayed_round_without_fresh_reads_is_the_jacobi_round(chunks, stale):
+    # every group reads the round's first residual: the same moves as the Jacobi round
+    prob = _small_problem(1, c=0.1, beta=2.0)
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=prob.n) * (rng.random(prob.n) < 0.3)
+    r = O.residual(prob, x)
+    idx = np.sort(rng.choice(prob.n, 23, replace=False))
+    xj, rj, mj = O.sca_round(prob, x, r, 1.3, 0.8, idx)
+    xd, rd, md = O.sca_round_delayed(prob, x, r, 1.3, 0.8, idx, chunks, stale)
+    np.testing.assert_allclose(xd, xj, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(rd, rj, rtol=0, atol=1e-13)
+    assert md == mj
+
+
+@pytest.mark.parametrize("c,beta", [(0.0, math.inf), (0.2, 1.5)])
+def test_delayed_one_coordinate_per_group_is_sequential_coordinate_descent(c, beta):
+    # stale = 0, one coordinate per group: each update sees all earlier ones.  Written out
+    # independently: residual recomputed from scratch, soft-threshold and clip inline.
+    prob = _small_problem(3, c=c, beta=beta)
+    A, b = np.asarray(prob.A), np.asarray(prob.b)
+    tau, gamma = 0.7, 0.9
+    rng = np.random.default_rng(4)
+    idx = np.sort(rng.choice(prob.n, 17, replace=False))
+    x = rng.normal(size=prob.n) * (rng.random(prob.n) < 0.4)
+    if np.isfinite(beta):
+        x = np.clip(x, -beta, beta)
+    xd, rd, _ = O.sca_round_delayed(prob, x, O.residual(prob, x), tau, gamma, idx, len(idx), 0)
+    y = x.copy()
+    for j in idx:
+        a = A[:, j]
+        g = a @ (A @ y - b) - 2.0 * c * y[j]
+        q = a @ a + tau
+        v = y[j] - g / q
+        t = np.sign(v) * max(abs(v) - prob.lam / q, 0.0)
+        t = min(max(t, -beta), beta)
+        y[j] += gamma * (t - y[j])
+    np.testing.assert_allclose(xd, y, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(rd, A @ y - b, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("chunks,stale", [(3, 0), (4, 1), (6, 2)])
+def test_delayed_rounds_reach_the_bruteforce_lasso_minimiser(chunks, stale):
+    rng = np.random.default_rng(7)
+    m, n = 12, 7
+    A = rng.normal(size=(m, n))
+    A /= np.linalg.norm(A, axis=0)
+    b = A @ np.array([1.5, 0, 0, -1.2, 0, 0.7, 0]) + 0.05 * rng.normal(size=m)
+    lam = 0.3 * np.max(np.abs(A.T @ b))
+    sols = _lasso_kkt_bruteforce(A, b, lam)
+    assert len(sols) == 1
+    prob = O.Problem(A=A, b=b, lam=lam, block_ptr=np.arange(n + 1))
+    cfg = O.RunConfig(tau=1.0, gamma=0.9, p=0.8, seed=5, delay_chunks=chunks,
+                      delay_stale=stale)
+    x, r, _ = O.run_rounds(prob, cfg, np.zeros(n), O.residual(prob, np.zeros(n)), 0, 3000)
+    np.testing.assert_allclose(x, sols[0], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(r, A @ x - b, rtol=0, atol=1e-12)
+
+
+def test_delayed_gauss_seidel_groups_descend():
+    # stale = 0: each group is a Jacobi step on a subset from the current point, so with
+    # gamma below 2 q_min / L (descent lemma) F never increases
+    prob = _small_problem(9, m=40, n=60)
+    A = np.asarray(prob.A)
+    L = np.linalg.eigvalsh(A.T @ A).max()
+    tau = L  # q_j = 1 + L > gamma L / 2 for gamma <= 1
+    cfg = O.RunConfig(tau=tau, gamma=1.0, p=0.6, seed=1, delay_chunks=5, delay_stale=0)
+    x = np.zeros(prob.n)
+    r = O.residual(prob, x)
+    F = O.objective(prob, x, r)
+    for k in range(60):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k, 1)
+        Fn = O.objective(prob, x, r)
+        assert Fn <= F + 1e-13
+        F = Fn
