@@ -80,7 +80,18 @@ typedef struct {
   double tol_rel_obj;    /* sca_solve: stop at (F - F_star)/|F_star| <= tol (0 = off)     */
   double F_star;         /* reference optimum for tol_rel_obj                              */
   double tol_merit;      /* sca_solve: stop at ||xh(x) - x||_inf <= tol (0 = off)          */
+  int64_t delay_chunks;  /* > 1: bounded-delay rounds (dense problems only; see below)     */
+  int64_t delay_stale;   /* staleness of the bounded-delay rounds, in groups (>= 0)        */
 } sca_opts;
+
+/* Bounded-delay rounds (delayed iterates of Algorithm 1, delays bounded as in Assumption
+ * D1): with delay_chunks = q > 1 the drawn coordinates of a round (ascending) are updated in
+ * q consecutive groups of ceil(|S|/q); group t reads the residual left by groups
+ * 0..t-1-delay_stale of the round, its own coordinates being current (D4).  Every update
+ * then misses at most (delay_stale + 1) * ceil(|S|/q) - 1 others.  q <= 1, or
+ * delay_stale >= q - 1, is the ordinary round (all drawn coordinates read the same
+ * iterate); delay_stale = 0 is a Gauss-Seidel sweep over the groups.  Deterministic.  The
+ * sparse, batched and multi-right-hand-side paths reject delay_chunks > 1 (SCA_EINVAL). */
 
 typedef struct {
   size_t struct_size;    /* = sizeof(sca_stats)                                          */

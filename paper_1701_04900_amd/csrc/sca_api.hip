@@ -56,6 +56,8 @@ sca_status sca::validate_opts(const sca_opts* o) {
     return set_error(SCA_EINVAL, "tau must be finite and >= 0");
   if (!(o->select_p > 0.0 && o->select_p <= 1.0))
     return set_error(SCA_EINVAL, "select_p must lie in (0, 1]");
+  if (o->delay_chunks < 0 || o->delay_chunks > (1 << 20) || o->delay_stale < 0)
+    return set_error(SCA_EINVAL, "delay_chunks must lie in [0, 2^20] and delay_stale be >= 0");
   return SCA_OK;
 }
 
@@ -200,6 +202,10 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
   ALLOC(p->d_state, sizeof(RoundState));
   ALLOC(p->d_sel_cols, sizeof(int) * n);
   ALLOC(p->d_dx_sel, es * n);
+  ALLOC(p->d_mbstate, sizeof(RoundState));
+  ALLOC(p->d_mbcols, sizeof(int) * n);
+  if (hipMemset(p->d_mbstate, 0, sizeof(RoundState)) != hipSuccess)
+    return set_error(SCA_EHIP, "memset of the group state failed");
   ALLOC(p->d_chunk_cnt, sizeof(int) * nch);
   ALLOC(p->d_J_idx, sizeof(int) * n);
   ALLOC(p->d_J_val, es * n);
@@ -226,7 +232,7 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
 }
 
 void sca::free_workspace(sca_problem* p) {
-  void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state,
+  void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state, p->d_mbstate, p->d_mbcols, p->d_ring,
                   p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
                   p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
                   p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
@@ -429,33 +435,24 @@ void sca::launch_select(sca_problem* p, const sca_opts* o, uint64_t Tthr, hipStr
                      o->instance, Tthr, p->d_state, p->d_sel_cols);
 }
 
+// S.2-S.4 on the coordinates listed in 'list' (count and step in *st), reading r.
 template <typename T>
-static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
-                               uint64_t Tthr, const BRParams& bp) {
-  const int m = (int)p->m, n = (int)p->n;
-  prof_begin(p, s, SCA_K_SELECT);
-  launch_select(p, o, Tthr, s);
-  prof_end(p, s, 0.0);
-  // Algorithmic bytes of the gradient pass: m*sizeof(T) per drawn coordinate (known on
-  // the host only in profiling mode, where it is computed from the expected count).
-  prof_begin(p, s, SCA_K_GRAD);
+static void grad_dense(sca_problem* p, T* x, const T* r, RoundState* st, const int* list,
+                       const BRParams& bp, hipStream_t s) {
+  const int m = (int)p->m;
   const dim3 ggrid(p->ncu * p->grad_wg_per_cu);
 #define GRAD_LAUNCH(UU)                                                                     \
   hipLaunchKernelGGL((k_grad_br<T, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,           \
-                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,         \
-                     p->d_state, (T*)p->d_dx_sel, bp)
+                     (long long)p->lda, m, r, x, p->d_cn2, list, st, (T*)p->d_dx_sel, bp)
 #define GRAD_WG_LAUNCH_NT(CC, UU, NTT)                                                      \
   hipLaunchKernelGGL((k_grad_br_wg<T, CC, UU, NTT>), ggrid, dim3(256), 0, s, (const T*)p->A, \
-                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
-                     p->d_state, (T*)p->d_dx_sel, bp)
+                     (long long)p->lda, m, r, x, p->d_cn2, list, st, (T*)p->d_dx_sel, bp)
 #define GRAD_WG_LAUNCH(CC, UU)                                                              \
   hipLaunchKernelGGL((k_grad_br_wg<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,      \
-                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
-                     p->d_state, (T*)p->d_dx_sel, bp)
+                     (long long)p->lda, m, r, x, p->d_cn2, list, st, (T*)p->d_dx_sel, bp)
 #define GRAD_WW_LAUNCH(CC, UU)                                                              \
   hipLaunchKernelGGL((k_grad_br_wwalk<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,   \
-                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols,          \
-                     p->d_state, (T*)p->d_dx_sel, bp)
+                     (long long)p->lda, m, r, x, p->d_cn2, list, st, (T*)p->d_dx_sel, bp)
   if (p->grad_kind == 3) {  // one wave per group of columns
     if (p->grad_cols == 4 && p->grad_unroll == 2)
       GRAD_WW_LAUNCH(4, 2);
@@ -497,16 +494,23 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
 #undef GRAD_WG_LAUNCH
 #undef GRAD_WG_LAUNCH_NT
 #undef GRAD_WW_LAUNCH
-  prof_end(p, s, 0.0);
+}
+
+// S.5: ordered list of the moved coordinates of 'list' (count in *st), then
+// out = base + sum of their columns times their moves (out may alias base).
+template <typename T>
+static void fold_dense(sca_problem* p, RoundState* st, const int* list, const T* base, T* out,
+                       hipStream_t s) {
+  const int m = (int)p->m, n = (int)p->n;
   prof_begin(p, s, SCA_K_COMPACT);
   const int nch = (n + kChunk - 1) / kChunk;
   const int cgrid = std::max(1, std::min(nch, 2 * p->ncu));
-  int* S_ptr = (int*)((char*)p->d_state + offsetof(RoundState, S_cnt));
+  int* S_ptr = (int*)((char*)st + offsetof(RoundState, S_cnt));
   hipLaunchKernelGGL(k_compact_count<T>, dim3(cgrid), dim3(1024), 0, s, (const T*)p->d_dx_sel,
                      (const int*)S_ptr, p->d_chunk_cnt);
   hipLaunchKernelGGL(k_compact_scatter<T>, dim3(cgrid), dim3(1024), 0, s,
-                     (const T*)p->d_dx_sel, (const int*)p->d_sel_cols, (const int*)S_ptr,
-                     (const int*)p->d_chunk_cnt, p->d_J_idx, (T*)p->d_J_val, p->d_state, 1);
+                     (const T*)p->d_dx_sel, list, (const int*)S_ptr, (const int*)p->d_chunk_cnt,
+                     p->d_J_idx, (T*)p->d_J_val, st, 1);
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_FOLD);
   constexpr int VN = V16<T>::N;
@@ -514,11 +518,99 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
   const int fgrid = std::max(1, std::min(nrt * kMaxGroups, 8 * p->ncu));
   hipLaunchKernelGGL((k_fold_partial<T, T>), dim3(fgrid), dim3(256), 0, s, (const T*)p->A,
                      (long long)p->lda, m, (const int*)p->d_J_idx, (const T*)p->d_J_val,
-                     (const RoundState*)p->d_state, (T*)p->d_part, (long long)p->ldp);
-  hipLaunchKernelGGL((k_fold_reduce<T, T, T>), dim3((m + 255) / 256), dim3(256), 0, s,
-                     (const T*)r, 1.0, (const T*)p->d_part, (long long)p->ldp,
-                     (const RoundState*)p->d_state, m, r, (double*)nullptr);
+                     (const RoundState*)st, (T*)p->d_part, (long long)p->ldp);
+  hipLaunchKernelGGL((k_fold_reduce<T, T, T>), dim3((m + 255) / 256), dim3(256), 0, s, base, 1.0,
+                     (const T*)p->d_part, (long long)p->ldp, (const RoundState*)st, m, out,
+                     (double*)nullptr);
   prof_end(p, s, 0.0);
+}
+
+template <typename T>
+static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
+                               uint64_t Tthr, const BRParams& bp) {
+  prof_begin(p, s, SCA_K_SELECT);
+  launch_select(p, o, Tthr, s);
+  prof_end(p, s, 0.0);
+  prof_begin(p, s, SCA_K_GRAD);
+  grad_dense<T>(p, x, r, p->d_state, p->d_sel_cols, bp, s);
+  prof_end(p, s, 0.0);
+  fold_dense<T>(p, p->d_state, p->d_sel_cols, r, r, s);
+}
+
+// ------------------------------------------------------------------ bounded-delay rounds
+// Group t of q: the drawn coordinates [t*per, min(S, (t+1)*per)), per = ceil(S/q), listed
+// in mb_cols with their count and the round's step in *mb.
+static __global__ void __launch_bounds__(1024)
+k_mb_window(const RoundState* __restrict__ st, int t, int q, const int* __restrict__ sel,
+            RoundState* __restrict__ mb, int* __restrict__ mb_cols) {
+  const int S = st->S_cnt;
+  const int per = (int)(((long long)S + q - 1) / q);
+  const int lo = (int)min((long long)S, (long long)t * per);
+  const int hi = min(S, lo + per);
+  for (int i = lo + (int)threadIdx.x; i < hi; i += 1024) mb_cols[i - lo] = sel[i];
+  if (threadIdx.x == 0) {
+    mb->S_cnt = hi - lo;
+    mb->work_ctr = 0;
+    mb->gamma_cur = st->gamma_cur;
+    mb->k = st->k;
+    mb->J_cnt = 0;
+    mb->G = 1;
+    mb->ngroups = 0;
+  }
+}
+
+static __global__ void k_mb_finish(RoundState* __restrict__ st, RoundState* __restrict__ mb) {
+  st->moved_updates += mb->moved_updates;
+  mb->moved_updates = 0;
+}
+
+template <typename T>
+static __global__ void k_copy_vec(const T* __restrict__ src, T* __restrict__ dst, int m) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+static sca_status ensure_ring(sca_problem* p, int slots) {
+  if (p->ring_slots >= slots) return SCA_OK;
+  if (p->d_ring) (void)hipFree(p->d_ring);
+  p->d_ring = nullptr;
+  p->ring_slots = 0;
+  sca_status st = dev_alloc(&p->d_ring, p->esize * (size_t)p->ldp * slots);
+  if (st != SCA_OK) return st;
+  p->ring_slots = slots;
+  return SCA_OK;
+}
+
+static int ring_slots_for(const sca_opts* o) {
+  const int64_t q = o->delay_chunks;
+  return (int)std::min<int64_t>(o->delay_stale, q) + 2;
+}
+
+template <typename T>
+static void launch_round_delayed(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
+                                 uint64_t Tthr, const BRParams& bp) {
+  const int m = (int)p->m;
+  const int q = (int)o->delay_chunks;
+  const int R = ring_slots_for(o);
+  const int64_t stale = o->delay_stale;
+  T* ring = (T*)p->d_ring;
+  auto slot = [&](int64_t v) { return ring + (size_t)(v % R) * p->ldp; };
+  const dim3 vgrid((unsigned)std::max(1, std::min((m + 255) / 256, 4 * p->ncu)));
+  prof_begin(p, s, SCA_K_SELECT);
+  launch_select(p, o, Tthr, s);
+  prof_end(p, s, 0.0);
+  hipLaunchKernelGGL(k_copy_vec<T>, vgrid, dim3(256), 0, s, (const T*)r, slot(0), m);
+  for (int t = 0; t < q; ++t) {
+    hipLaunchKernelGGL(k_mb_window, dim3(1), dim3(1024), 0, s, (const RoundState*)p->d_state, t,
+                       q, (const int*)p->d_sel_cols, p->d_mbstate, p->d_mbcols);
+    prof_begin(p, s, SCA_K_GRAD);
+    grad_dense<T>(p, x, slot(std::max<int64_t>(0, t - stale)), p->d_mbstate, p->d_mbcols, bp,
+                  s);
+    prof_end(p, s, 0.0);
+    fold_dense<T>(p, p->d_mbstate, p->d_mbcols, slot(t), slot(t + 1), s);
+  }
+  hipLaunchKernelGGL(k_copy_vec<T>, vgrid, dim3(256), 0, s, (const T*)slot(q), r, m);
+  hipLaunchKernelGGL(k_mb_finish, dim3(1), dim3(1), 0, s, p->d_state, p->d_mbstate);
 }
 
 // Fresh residual with FP64 accumulation: r64 = A x - b (and r_out in the dtype if given).
@@ -577,9 +669,12 @@ static void run_rounds_t(sca_problem* p, const sca_opts* o, int64_t nrounds, T* 
                          hipStream_t s) {
   const uint64_t Tthr = selection_threshold(o->select_p);
   const BRParams bp = make_brparams(p, o->tau);
+  const bool delayed = o->delay_chunks > 1 && o->delay_stale < o->delay_chunks - 1;
   for (int64_t i = 0; i < nrounds; ++i) {
     if (p->sparse)
       launch_round_csc(p, o, (void*)x, (void*)r, s, Tthr, bp);
+    else if (delayed)
+      launch_round_delayed<T>(p, o, x, r, s, Tthr, bp);
     else
       launch_round_dense<T>(p, o, x, r, s, Tthr, bp);
   }
@@ -631,12 +726,21 @@ void sca::init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begi
 }
 
 // ------------------------------------------------------------------ public entry points
+// Bounded-delay rounds: dense problems only; their residual versions are allocated here
+// (outside any graph capture).
+static sca_status prepare_delay(sca_problem* p, const sca_opts* o) {
+  if (o->delay_chunks <= 1) return SCA_OK;
+  if (p->sparse) return set_error(SCA_EINVAL, "bounded-delay rounds need a dense problem");
+  return ensure_ring(p, ring_slots_for(o));
+}
+
 extern "C" sca_status sca_step(sca_problem* p, const sca_opts* o, int64_t round_begin,
                                int64_t nrounds, void* x, void* r, void* stream) {
   if (!p) return set_error(SCA_EINVAL, "problem is NULL");
   sca_status st = validate_opts(o);
   if (st != SCA_OK) return st;
   if ((st = check_tau(p, o->tau)) != SCA_OK) return st;
+  if ((st = prepare_delay(p, o)) != SCA_OK) return st;
   if (round_begin < 0 || nrounds < 0) return set_error(SCA_EINVAL, "negative round range");
   if (!x || !r) return set_error(SCA_EINVAL, "x or r is NULL");
   if (((uintptr_t)r) % 16) return set_error(SCA_EINVAL, "r must be 16-byte aligned");
@@ -718,11 +822,13 @@ extern "C" sca_status sca_objective(sca_problem* p, const sca_opts* o, const voi
 // (into d_scal[0]); rebuilt when any baked-in argument changes.
 static sca_status solve_graph(sca_problem* p, const sca_opts* o, void* x, void* r,
                               const BRParams& bp) {
-  const double key[12] = {(double)(uintptr_t)x, (double)(uintptr_t)r, (double)o->check_every,
+  const double key[14] = {(double)(uintptr_t)x, (double)(uintptr_t)r, (double)o->check_every,
                           o->select_p, (double)o->seed, (double)o->instance, o->tau, p->lam,
-                          p->c, p->beta, (double)p->reg, p->theta};
+                          p->c, p->beta, (double)p->reg, p->theta, (double)o->delay_chunks,
+                          (double)o->delay_stale};
   bool same = p->sgraph != nullptr;
-  for (int i = 0; same && i < 12; ++i) same = key[i] == p->skey[i] || (key[i] != key[i] && p->skey[i] != p->skey[i]);
+  for (int i = 0; same && i < 14; ++i)
+    same = key[i] == p->skey[i] || (key[i] != key[i] && p->skey[i] != p->skey[i]);
   if (same) return SCA_OK;
   if (p->sgraph) {
     (void)hipGraphExecDestroy(p->sgraph);
@@ -746,7 +852,7 @@ static sca_status solve_graph(sca_problem* p, const sca_opts* o, void* x, void* 
     p->sgraph = nullptr;
     return set_error(SCA_EHIP, "graph instantiation failed");
   }
-  for (int i = 0; i < 12; ++i) p->skey[i] = key[i];
+  for (int i = 0; i < 14; ++i) p->skey[i] = key[i];
   return SCA_OK;
 }
 
@@ -757,6 +863,7 @@ extern "C" sca_status sca_solve(sca_problem* p, const sca_opts* o, void* x, sca_
   sca_status st = validate_opts(o);
   if (st != SCA_OK) return st;
   if ((st = check_tau(p, o->tau)) != SCA_OK) return st;
+  if ((st = prepare_delay(p, o)) != SCA_OK) return st;
   if (!x) return set_error(SCA_EINVAL, "x is NULL");
   if (stats && stats->struct_size != sizeof(sca_stats))
     return set_error(SCA_EINVAL, "stats.struct_size mismatch");

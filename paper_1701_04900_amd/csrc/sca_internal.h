@@ -71,7 +71,13 @@ struct sca_problem {
   // graph of check_every rounds + objective used by sca_solve (built on first use)
   hipStream_t cap = nullptr;
   hipGraphExec_t sgraph = nullptr;
-  double skey[12] = {0};
+  double skey[14] = {0};
+
+  // bounded-delay rounds: state and list of the group in flight, residual versions
+  sca::RoundState* d_mbstate = nullptr;
+  int* d_mbcols = nullptr;
+  void* d_ring = nullptr;
+  int ring_slots = 0;
 
   // profiling
   bool profiling = false;

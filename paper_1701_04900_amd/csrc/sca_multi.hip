@@ -915,6 +915,8 @@ extern "C" sca_status sca_multi_step(sca_multi* M, const sca_opts* o, int64_t ro
   if (!M) return set_error(SCA_EINVAL, "NULL argument");
   sca_status st = mcheck_opts(M, o);
   if (st != SCA_OK) return st;
+  if (o->delay_chunks > 1)
+    return set_error(SCA_EINVAL, "bounded-delay rounds need the single-problem dense path");
   if (!X || !R || round_begin < 0 || nrounds < 0)
     return set_error(SCA_EINVAL, "X or R is NULL, or a negative round count");
   if (((uintptr_t)R) % 16) return set_error(SCA_EINVAL, "R must be 16-byte aligned");
@@ -1004,6 +1006,8 @@ extern "C" sca_status sca_multi_solve(sca_multi* M, const sca_opts* o, void* X,
   if (!M || !X) return set_error(SCA_EINVAL, "NULL argument");
   sca_status st = mcheck_opts(M, o);
   if (st != SCA_OK) return st;
+  if (o->delay_chunks > 1)
+    return set_error(SCA_EINVAL, "bounded-delay rounds need the single-problem dense path");
   if (o->max_rounds < 0 || o->check_every < 1)
     return set_error(SCA_EINVAL, "max_rounds >= 0 and check_every >= 1");
   if (stats)

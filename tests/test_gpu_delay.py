@@ -1,0 +1,129 @@
+"""GPU parity of the bounded-delay rounds (groups of drawn coordinates reading the residual
+left by earlier groups, delays bounded as in Assumption D1) against the FP64 CPU oracle's
+delayed rounds; the limit of the delayed iteration against the ordinary one."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sca_oracle as O
+from paper_1701_04900_amd import inputs, sca
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
+
+
+def _run_gpu(w, P, o, rounds, every):
+    x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+    r = torch.empty(w.m, dtype=w.dtype, device="cuda")
+    sca.sca_residual(P.handle, x, r)
+    out = []
+    for k0 in range(0, rounds, every):
+        sca.sca_step(P.handle, o, k0, every, x, r)
+        torch.cuda.synchronize()
+        out.append((x.double().cpu().numpy(), r.double().cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("q,s,c_frac,beta", [(4, 0, 0.0, math.inf), (5, 1, 0.0, math.inf),
+                                             (8, 3, 0.2, 2.0), (3, 7, 0.0, math.inf),
+                                             (13, 0, 0.0, math.inf)])
+def test_delayed_rounds_match_oracle_fp64(q, s, c_frac, beta):
+    print(f"[gpu] bounded-delay rounds q={q} stale={s}", flush=True)
+    w = inputs.dense_problem(200, 900, nnz_frac=0.03, lam_frac=0.05, c_frac=c_frac, beta=beta,
+                             block=10, p=0.6, dtype=torch.float64, seed=40 + q)
+    wd = w.to("cuda")
+    P = sca.Problem.from_workload(wd)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, delay_chunks=q,
+                      delay_stale=s)
+    gpu = _run_gpu(wd, P, o, 20, 5)
+    prob = O.Problem(A=w.A_numpy(), b=w.b.numpy(), lam=w.lam, c=w.c, beta=w.beta,
+                     block_ptr=w.block_ptr)
+    cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed, delay_chunks=q,
+                      delay_stale=s)
+    x = np.zeros(w.n)
+    r = O.residual(prob, x)
+    for i, k0 in enumerate(range(0, 20, 5)):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k0, 5)
+        assert _rel(gpu[i][0], x) <= 1e-10 and _rel(gpu[i][1], r) <= 1e-10, (q, s, k0)
+    P.close()
+
+
+def test_delayed_rounds_fp32_objective():
+    w = inputs.dense_problem(2000, 8000, nnz_frac=0.02, lam_frac=0.02, block=32, p=0.3,
+                             dtype=torch.float32, seed=47)
+    wd = w.to("cuda")
+    P = sca.Problem.from_workload(wd)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, delay_chunks=6,
+                      delay_stale=1)
+    gpu = _run_gpu(wd, P, o, 30, 10)
+    prob = O.Problem(A=w.A_numpy(), b=w.b.double().numpy(), lam=w.lam, block_ptr=w.block_ptr)
+    cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed, delay_chunks=6,
+                      delay_stale=1)
+    x = np.zeros(w.n)
+    r = O.residual(prob, x)
+    for i, k0 in enumerate(range(0, 30, 10)):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k0, 10)
+        Fo = O.objective(prob, x, r)
+        Fg = sca.sca_objective(P.handle, o, torch.from_numpy(gpu[i][0]).float().cuda())["F"]
+        assert abs(Fg - Fo) <= 1e-4 * abs(Fo), (k0, Fg, Fo)
+    P.close()
+
+
+def test_delayed_solve_reaches_the_same_lasso_minimiser_and_is_reproducible():
+    w = inputs.dense_problem(300, 1000, nnz_frac=0.02, lam_frac=0.1, block=20, p=0.5,
+                             dtype=torch.float64, seed=48).to("cuda")
+    P = sca.Problem.from_workload(w)
+    base = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, max_rounds=50000,
+                check_every=20, tol_merit=1e-12)
+    xj = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    sca.sca_solve(P.handle, sca.make_opts(**base), xj)
+    for q, s in ((4, 0), (6, 2)):
+        o = sca.make_opts(**base, delay_chunks=q, delay_stale=s)
+        x1 = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+        st = sca.sca_solve(P.handle, o, x1)
+        assert st["merit"] <= 1e-12
+        assert float((x1 - xj).abs().max()) <= 1e-9 * max(1.0, float(xj.abs().max()))
+        x2 = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+        sca.sca_solve(P.handle, o, x2)
+        assert torch.equal(x1, x2)
+    P.close()
+
+
+def test_delayed_graph_solve_equals_eager_steps():
+    w = inputs.dense_problem(150, 500, nnz_frac=0.04, lam_frac=0.05, block=8, p=0.7,
+                             dtype=torch.float64, seed=49).to("cuda")
+    P = sca.Problem.from_workload(w)
+    kw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, delay_chunks=5, delay_stale=1)
+    xs = _run_gpu(w, P, sca.make_opts(**kw), 40, 40)[-1][0]
+    xg = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    sca.sca_solve(P.handle, sca.make_opts(**kw, max_rounds=40, check_every=10), xg,
+                  raise_on_notconv=False)
+    assert np.array_equal(xg.cpu().numpy(), xs)
+    P.close()
+
+
+def test_delayed_rounds_are_rejected_outside_the_dense_path():
+    s = inputs.sparse_problem(200, 800, per_col=4, nnz_frac=0.02, block=32, p=0.5,
+                              dtype=torch.float64, seed=2).to("cuda")
+    PS = sca.Problem.from_workload(s)
+    xs = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    rs = torch.zeros(s.m, dtype=torch.float64, device="cuda")
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_step(PS.handle, sca.make_opts(tau=s.tau, delay_chunks=4), 0, 1, xs, rs)
+    assert e.value.status == sca.SCA_EINVAL
+    w = inputs.multi_rhs_problem(64, 200, 3, dtype=torch.float64, seed=16, block=10)
+    M = sca.Multi(w.At.cuda(), w.m, w.B.cuda(), w.lams, block_ptr=w.block_ptr)
+    X, R = M.zeros_x(), M.empty_r()
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_multi_step(M.handle, sca.make_opts(tau=w.tau, delay_chunks=4), 0, 1, X, R)
+    assert e.value.status == sca.SCA_EINVAL
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_step(PS.handle, sca.make_opts(tau=s.tau, delay_chunks=-1), 0, 1, xs, rs)
+    assert e.value.status == sca.SCA_EINVAL
