@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -320,6 +321,51 @@ def bench_multi(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_delay(args):
+    """Bounded-delay rounds on the 20000 x 100000 FP32 LASSO: rounds and time to relative
+    error 1e-6 for several (groups q, staleness s); every update misses at most
+    (s + 1) ceil(|S|/q) - 1 others (|S| ~ 25000 drawn coordinates per round)."""
+    w = inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")
+    okw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+    F_star, _ = reference_optimum(w, okw)
+    P = sca.Problem.from_workload(w)
+    S_mean = w.p * w.n
+    rows = []
+    value = None
+    for q, st_ in [(1, 0), (2, 0), (4, 0), (4, 1), (16, 0), (16, 3), (64, 0)]:
+        o = sca.make_opts(**okw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
+                          F_star=F_star, delay_chunks=q, delay_stale=st_)
+        x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+        sca.sca_solve(P.handle, o, x)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for _ in range(args.steps):
+            x.zero_()
+            stats.append(sca.sca_solve(P.handle, o, x))
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        upd = stats[-1]["coord_updates"]
+        delta = (st_ + 1) * math.ceil(S_mean / q) - 1 if q > 1 else int(S_mean) - 1
+        rows.append(dict(groups=q, stale=st_, delay_bound=delta, rounds=stats[-1]["rounds"],
+                         time_to_tol_s=el, coord_updates_per_s=upd / el,
+                         rel_err=stats[-1]["rel_err"]))
+        log(f"q={q} s={st_}: delay bound {delta}, {stats[-1]['rounds']} rounds, {el * 1e3:.1f} ms")
+        if q == 1:
+            value = upd / el
+            base_ms = el * 1e3
+    out = {
+        "metric": METRIC, "value": value, "unit": "coord-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": base_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"delay_study_lasso_dense_{w.m}x{w.n}_fp32", "m": w.m, "n": w.n,
+                   "block": 64, "select_p": w.p, "gamma": w.gamma, "tol_rel_obj": args.tol,
+                   "step": "one solve from x=0 to tolerance per (groups, staleness)"},
+        "delay_study": rows, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_grad_br_wg_lasso_20000x100000_fp32.txt")
 CALIB_BYTES = 1 << 30
 
@@ -440,7 +486,8 @@ def main():
                     help="rounds per step of the box-nonconvex workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["lasso", "nonconvex", "sparse", "batch", "multi"],
+    ap.add_argument("--workload", choices=["lasso", "nonconvex", "sparse", "batch", "multi",
+                                          "delay"],
                     default="lasso")
     ap.add_argument("--rhs", type=int, default=64, help="right-hand sides of --workload multi")
     ap.add_argument("--instances", type=int, default=256)
@@ -464,6 +511,9 @@ def main():
         return
     if args.workload == "multi":
         bench_multi(args)
+        return
+    if args.workload == "delay":
+        bench_delay(args)
         return
     if args.pmc_probe:
         pmc_probe(args)
@@ -494,7 +544,7 @@ def sparse_reference_optimum(w, opts_kw):
 
 def grad_kernel_name(L, sparse):
     if sparse:
-        return "k_grad_br_csc<float>"
+        return "k_grad_br_cscp<float,8>"
     return {0: f"k_grad_br<float,{L['grad_unroll']}>",
             1: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},true>",
             2: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},false>",

@@ -395,21 +395,37 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
 }
 
 // out[j][r] = scale * base[j][r] + sum over the kMFS partials (fixed order), j < K, r < m;
-// out and out64 may each be NULL (out may alias base).
+// out and out64 may each be NULL (out may alias base).  Tiles of 64 rows: the partials are
+// read row by row (contiguous over the problems), summed, transposed through LDS and
+// written column by column.
+constexpr int kRT = 64;
 template <typename TB, typename TP, typename TO>
 __global__ void __launch_bounds__(256)
 k_mfold_reduce(const TP* __restrict__ P, long long ldp, int m, int K, int KP, const TB* base,
                long long ldbase, double scale, TO* out, long long ldout,
                double* __restrict__ out64, long long ld64) {
-  const long long total = (long long)m * K;
-  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
-       q += (long long)gridDim.x * blockDim.x) {
-    const int j = (int)(q / m), r = (int)(q % m);
-    TP s = (TP)0;
-    for (int sp = 0; sp < kMFS; ++sp) s += P[(size_t)sp * ldp + (size_t)r * KP + j];
-    const double v = scale * (double)base[(size_t)j * ldbase + r] + (double)s;
-    if (out) out[(size_t)j * ldout + r] = (TO)v;
-    if (out64) out64[(size_t)j * ld64 + r] = v;
+  __shared__ TP tile[kRT][kMaxK + 1];
+  for (int rt = blockIdx.x; rt * kRT < m; rt += gridDim.x) {
+    const int r0 = rt * kRT;
+    for (int q = threadIdx.x; q < kRT * KP; q += 256) {
+      const int rr = q / KP, j = q % KP;
+      const int r = r0 + rr;
+      TP s = (TP)0;
+      if (r < m)
+        for (int sp = 0; sp < kMFS; ++sp) s += P[(size_t)sp * ldp + (size_t)r * KP + j];
+      tile[rr][j] = s;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kRT * K; q += 256) {
+      const int j = q / kRT, rr = q % kRT;
+      const int r = r0 + rr;
+      if (r < m) {
+        const double v = scale * (double)base[(size_t)j * ldbase + r] + (double)tile[rr][j];
+        if (out) out[(size_t)j * ldout + r] = (TO)v;
+        if (out64) out64[(size_t)j * ld64 + r] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -663,7 +679,7 @@ void mround(sca_multi* M, const sca_opts* o, T* X, T* R, hipStream_t s, uint64_t
   mprof_end(M, s);
   mprof_begin(M, s, SCA_K_FOLD);
   launch_mfold<T, T, T>(M, (const T*)M->d_D, M->d_sel, (T*)M->d_Rp, s);
-  const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>((M->m * K + 255) / 256, 4 * M->ncu));
+  const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>((M->m + kRT - 1) / kRT, 8 * M->ncu));
   hipLaunchKernelGGL((k_mfold_reduce<T, T, T>), dim3(rgrid), dim3(256), 0, s, (const T*)M->d_Rp,
                      ldp_of(M), (int)M->m, K, KP, (const T*)R, (long long)M->lda, 1.0, R,
                      (long long)M->lda, (double*)nullptr, 0ll);
@@ -681,7 +697,7 @@ void mresidual(sca_multi* M, const T* X, T* R_out, hipStream_t s) {
   mcompact<T>(M, (const T*)M->d_mv, M->d_nall, 0, s);
   launch_mfold<T, double, double>(M, (const double*)M->d_Xt, (const int*)nullptr,
                                   (double*)M->d_Rp, s);
-  const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>((M->m * K + 255) / 256, 4 * M->ncu));
+  const int rgrid = (int)std::max<int64_t>(1, std::min<int64_t>((M->m + kRT - 1) / kRT, 8 * M->ncu));
   hipLaunchKernelGGL((k_mfold_reduce<T, double, T>), dim3(rgrid), dim3(256), 0, s,
                      (const double*)M->d_Rp, ldp_of(M), (int)M->m, K, KP, (const T*)M->B,
                      (long long)M->ldb, -1.0, R_out, (long long)M->lda, M->d_R64,
