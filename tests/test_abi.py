@@ -89,3 +89,14 @@ def test_create_dense_rejects_bad_arguments_on_host(L, case):
     assert st == sca.SCA_EINVAL
     assert h.value is None
     assert L.sca_last_error().decode()
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus N with N > 1 exits with a message (no GPU needed)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
