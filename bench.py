@@ -281,19 +281,23 @@ def bench_multi(args):
                          fold_TFLOPs=round(ffl / (f["ms"] * 1e-3) / 1e12, 2) if f["ms"] else None)
         log(f"profiled pass: {prof_pass}, roofline {roof}")
     # the same K problems, one single-problem solve after another
-    plain_t, plain_upd = 0.0, 0
-    probs = [sca.Problem.dense(w.At, w.m, w.B[k, : w.m], float(w.lams[k]), w.c, w.beta,
-                               w.block_ptr) for k in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k, P in enumerate(probs):
-        ok = sca.make_opts(**okw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
-                           F_star=F_star[k])
-        xk = torch.zeros(w.n, dtype=torch.float32, device="cuda")
-        plain_upd += sca.sca_solve(P.handle, ok, xk)["coord_updates"]
-    torch.cuda.synchronize()
-    plain_t = time.perf_counter() - t0
-    log(f"single-problem solves one after another: {plain_t * 1e3:.1f} ms")
+    plain_t, plain_upd = float("nan"), 0
+    if args.no_compare:
+        probs = []
+    else:
+        plain_t, plain_upd = 0.0, 0
+        probs = [sca.Problem.dense(w.At, w.m, w.B[k, : w.m], float(w.lams[k]), w.c, w.beta,
+                                   w.block_ptr) for k in range(K)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, P in enumerate(probs):
+            ok = sca.make_opts(**okw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
+                               F_star=F_star[k])
+            xk = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+            plain_upd += sca.sca_solve(P.handle, ok, xk)["coord_updates"]
+        torch.cuda.synchronize()
+        plain_t = time.perf_counter() - t0
+        log(f"single-problem solves one after another: {plain_t * 1e3:.1f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         w1 = inputs.DenseWorkload(w.name, w.At, w.m, w.n, w.lda, w.B[K // 2, : w.m],
@@ -313,9 +317,9 @@ def bench_multi(args):
                    "step": "one multi solve of all K problems from X=0"},
         "max_rel_err": max(s["rel_err"] for s in stats[-1]),
         "rounds_to_all": rounds,
-        "plain_sequential": {"time_to_all_tol_s": plain_t,
-                             "coord_updates_per_s": plain_upd / plain_t},
-        "multi_speedup": plain_t / (elapsed / args.steps),
+        "plain_sequential": None if args.no_compare else
+        {"time_to_all_tol_s": plain_t, "coord_updates_per_s": plain_upd / plain_t},
+        "multi_speedup": None if args.no_compare else plain_t / (elapsed / args.steps),
         "roofline": roof, "profiled_pass": prof_pass, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -490,6 +494,8 @@ def main():
                                           "delay"],
                     default="lasso")
     ap.add_argument("--rhs", type=int, default=64, help="right-hand sides of --workload multi")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="--workload multi: skip the single-problem solves it is compared with")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_JSON"))

@@ -72,10 +72,10 @@ namespace {
 
 constexpr int kMTC = 128;  // gradient tile: drawn coordinates per workgroup
 constexpr int kMKC = 32;   // gradient: rows of R staged per LDS chunk
-constexpr int kMNS = 8;    // gradient: row splits (partials reduced in the best response)
+constexpr int kMNS = 16;   // gradient: row splits (partials reduced in the best response)
 constexpr int kMFR = 256;  // fold tile: rows per workgroup (64 per wave)
 constexpr int kMEC = 32;   // fold: list entries staged per LDS chunk
-constexpr int kMFS = 8;    // fold: list splits (partials reduced in the fold reduction)
+constexpr int kMFS = 32;   // fold: list splits (partials reduced in the fold reduction)
 constexpr int kMaxK = 64;
 
 // 16x16x4 MFMA: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k; element (i, j) of
