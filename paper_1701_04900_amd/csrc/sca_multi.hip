@@ -158,7 +158,7 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
 #pragma unroll
       for (int s = 0; s < NST; ++s) acc[c][s] = (typename M::acc){0, 0, 0, 0};
     for (int r0 = rlo; r0 < rhi; r0 += kMKC) {
-      // this lane's A quads of the chunk (issued before the R copy so the latencies overlap)
+      // this lane's A quads of the chunk (issued first, so that the latencies overlap)
       Quad<TM> a[kMKC / 16][2];
 #pragma unroll
       for (int step = 0; step < kMKC / 16; ++step) {
@@ -181,25 +181,36 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
           }
         }
       }
-      __syncthreads();
-      // R rows r0..r0+kMKC-1 of every problem into LDS (zeros past the split and past K)
-      for (int q = threadIdx.x; q < KP * (kMKC / 4); q += 256) {
-        const int j = q / (kMKC / 4), rr = 4 * (q % (kMKC / 4));
-        Quad<TM> v;
+      // this thread's quads of R rows r0..r0+kMKC-1 (zeros past the split and past K), also
+      // loaded before the barrier
+      constexpr int NQ = (KP * (kMKC / 4) + 255) / 256;
+      Quad<TM> rq[NQ];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v.v[u] = (TM)0;
-        if (j < K) {
+      for (int i = 0; i < NQ; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        const int j = q / (kMKC / 4), rr = 4 * (q % (kMKC / 4));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rq[i].v[u] = (TM)0;
+        if (q < KP * (kMKC / 4) && j < K) {
           const int r = r0 + rr;
           if (r + 3 < rhi) {
-            v = load_quad<TM>(R + (size_t)j * ldr + r);
+            rq[i] = load_quad<TM>(R + (size_t)j * ldr + r);
           } else {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-              if (r + u < rhi) v.v[u] = R[(size_t)j * ldr + r + u];
+              if (r + u < rhi) rq[i].v[u] = R[(size_t)j * ldr + r + u];
           }
         }
+      }
+      __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s_r[j][rr + u] = v.v[u];
+      for (int i = 0; i < NQ; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        if (q < KP * (kMKC / 4)) {
+          const int j = q / (kMKC / 4), rr = 4 * (q % (kMKC / 4));
+#pragma unroll
+          for (int u = 0; u < 4; ++u) s_r[j][rr + u] = rq[i].v[u];
+        }
       }
       __syncthreads();
 #pragma unroll
