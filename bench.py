@@ -144,8 +144,23 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
     upd_batch = sum(s["coord_updates"] for s in st)
+    # algorithmic bytes of the gradient pass of one batched solve: m_k * 4 B per drawn
+    # coordinate of instance k
+    grad_bytes = float(sum(s["coord_updates"] * w.m * 4 for s, w in zip(st, ws)))
     log(f"batched solve: {t_batch * 1e3:.1f} ms, rounds max {max(s['rounds'] for s in st)}, "
         f"max rel err {max(s['rel_err'] for s in st):.2e}")
+    if args.no_compare:
+        out = {
+            "metric": METRIC, "value": upd_batch / t_batch, "unit": "coord-updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"batch_{K}_lasso_m500-8000_n5m_fp32", "instances": K,
+                       "A_bytes": abytes, "tol_rel_obj": args.tol},
+            "grad_alg_bytes_per_solve": grad_bytes,
+            "max_rel_err": max(s["rel_err"] for s in st)}
+        print(json.dumps(out), flush=True)
+        return
     # the same instances, one plain solve after another
     plain_t, plain_upd, plain_x = 0.0, 0, []
     probs = [sca.Problem.from_workload(w) for w in ws]
@@ -187,7 +202,8 @@ def bench_batch(args):
                    "A_bytes": abytes, "block": 64, "select_p": p, "gamma": gamma,
                    "tol_rel_obj": args.tol, "step": "one batched solve of every instance"},
         "batched": {"time_to_all_tol_s": t_batch, "coord_updates_per_s": upd_batch / t_batch,
-                    "max_rel_err": max(s["rel_err"] for s in st)},
+                    "max_rel_err": max(s["rel_err"] for s in st),
+                    "grad_alg_bytes_per_solve": grad_bytes},
         "plain_sequential": {"time_to_all_tol_s": plain_t,
                              "coord_updates_per_s": plain_upd / plain_t},
         "batched_speedup": plain_t / t_batch,
@@ -495,7 +511,8 @@ def main():
                     default="lasso")
     ap.add_argument("--rhs", type=int, default=64, help="right-hand sides of --workload multi")
     ap.add_argument("--no-compare", action="store_true",
-                    help="--workload multi: skip the single-problem solves it is compared with")
+                    help="--workload multi / batch: skip the single-problem solves they are "
+                         "compared with")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--pmc-summarize", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_JSON"))
