@@ -386,7 +386,7 @@ def bench_delay(args):
     print(json.dumps(out), flush=True)
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_grad_br_wg_lasso_20000x100000_fp32.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_grad_br_fold_lasso_20000x100000_fp32.txt")
 CALIB_BYTES = 1 << 30
 
 
@@ -416,7 +416,8 @@ def pmc_probe(args):
     x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
     st = sca.sca_solve(P.handle, o, x)
     print(json.dumps(dict(rounds=st["rounds"], coord_updates=st["coord_updates"],
-                          launch=sca.sca_problem_get_launch(P.handle), m=w.m)), flush=True)
+                          launch=sca.sca_problem_get_launch(P.handle), m=w.m,
+                          groups=fused_groups())), flush=True)
 
 
 def pmc_summarize(fetch_dir, write_dir, probe_json):
@@ -445,10 +446,12 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
     launches = res["FETCH_SIZE"]["launches"]
     fetch_b = res["FETCH_SIZE"]["grad_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
     write_b = res["WRITE_SIZE"]["grad_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
-    alg_b = probe["coord_updates"] / probe["rounds"] * probe["m"] * 4
+    alg_b = round_alg_bytes(probe["launch"], probe["coord_updates"] / probe["rounds"],
+                            probe["m"], 4, probe.get("groups", 0))
     fp = kernel_fingerprint(probe["launch"])
     lines = [
-        "# HBM traffic of the gradient kernel, LASSO 20000x100000 FP32 (rocprofv3 counters)",
+        "# HBM traffic of the dominant round kernel, LASSO 20000x100000 FP32 (rocprofv3 "
+        "counters)",
         "",
         "Commands (repository root, one MI355X; each counter in a run of its own):",
         "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -- "
@@ -565,9 +568,31 @@ def sparse_reference_optimum(w, opts_kw):
     return st["F"], st
 
 
-def grad_kernel_name(L, sparse):
+def fused_groups():
+    """Workgroups (= fold partials) of the fused dense round: one per CU, at most 256."""
+    return min(torch.cuda.get_device_properties(0).multi_processor_count, 256)
+
+
+def fused_q(m, esize):
+    """16-byte row groups per thread when a 1024-thread workgroup holds an m-row column."""
+    groups = (m * esize + 15) // 16
+    return (groups + 1023) // 1024
+
+
+def round_alg_bytes(L, drawn, m, esize, groups):
+    """Algorithmic bytes of one launch of the gradient kernel: the drawn columns once;
+    the fused kind also writes one m-vector of fold partials per workgroup."""
+    b = drawn * m * esize
+    if L["grad_kind"] == 4:
+        b += groups * m * esize
+    return b
+
+
+def grad_kernel_name(L, sparse, m=0):
     if sparse:
         return "k_grad_br_cscp<float,8>"
+    if L["grad_kind"] == 4:
+        return f"k_grad_br_fold<float,{fused_q(m, 4)},{L['grad_cols']}>"
     return {0: f"k_grad_br<float,{L['grad_unroll']}>",
             1: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},true>",
             2: f"k_grad_br_wg<float,{L['grad_cols']},{L['grad_unroll']},false>",
@@ -672,7 +697,13 @@ def bench_single(args):
         g, f = prof["grad"], prof["fold"]
         grad_b = float(pupd) * bytes_per_update
         fold_b = float(pmoved) * bytes_per_update
-        cands = [("grad", g, grad_b, grad_kernel_name(L, sparse))]
+        if not sparse and L["grad_kind"] == 4:
+            # fused round: the partials written by the gradient kernel, then read (with r
+            # read and written) by the partial reduction in place of the fold
+            G = fused_groups()
+            grad_b = round_alg_bytes(L, float(pupd) / g["launches"], w.m, esize, G) * g["launches"]
+            fold_b = float(f["launches"]) * (G + 2) * w.m * esize
+        cands = [("grad", g, grad_b, grad_kernel_name(L, sparse, w.m))]
         if sparse:
             cands.append(("fold", f, fold_b, "k_fold_csc<float> + k_fold_csc_finish<float>"))
         step, kp, kb, kname = max(cands, key=lambda c: c[1]["ms"])

@@ -211,6 +211,13 @@ sca_status sca_profile_get(sca_problem* p, double* ms_host, int64_t* launches_ho
  *  grad_kind 2: as 1 with ordinary loads, (cols, unroll) in {(8,2), (16,1)};
  *  grad_kind 3: every wave walks its own group of grad_cols columns (short columns),
  *    (cols, unroll) in {(4,2), (4,4), (8,1)};
+ *  grad_kind 4: fused round of a dense problem (steps S.2-S.5 of Algorithm 1 in one pass
+ *    over the drawn columns): one 1024-thread workgroup per compute unit holds a whole
+ *    column, r and its own fold partial in registers and walks its share of the drawn list
+ *    grad_cols columns at a time; a second kernel adds the partials to r.  Needs
+ *    m <= 20480 (FP32) or m <= 6144 (FP64); grad_cols in {1, 2, 4, 8} is reduced to the
+ *    largest group the registers hold for this m; grad_unroll = grad_wg_per_cu = 1.
+ *    Rounds with bounded delay (delay_chunks > 1) run the two-pass kernels instead.
  *  grad_wg_per_cu in [1, 16]: persistent workgroups per compute unit. */
 typedef struct {
   size_t struct_size; /* = sizeof(sca_launch) */
@@ -232,7 +239,9 @@ typedef struct {
  * created afterwards take the first matching row, else the built-in default. */
 sca_status sca_tuning_set(const sca_tune_entry* entries_host, int64_t count);
 
-/* Read / override the launch shape of one problem.  Rejects shapes outside the lists above. */
+/* Read / override the launch shape of one problem.  Rejects shapes outside the lists above
+ * and the fused kind where the problem cannot take it (sparse, or m too large); the shape
+ * read back is the one in effect. */
 sca_status sca_problem_get_launch(sca_problem* p, sca_launch* out);
 sca_status sca_problem_set_launch(sca_problem* p, const sca_launch* launch);
 

@@ -108,9 +108,47 @@ static bool launch_valid(const sca_launch* l) {
       return (c == 8 && u == 2) || (c == 16 && u == 1);
     case 3:
       return (c == 4 && (u == 2 || u == 4)) || (c == 8 && u == 1);
+    case 4:
+      return (c == 1 || c == 2 || c == 4 || c == 8) && u == 1 && l->grad_wg_per_cu == 1;
     default:
       return false;
   }
+}
+
+// Fused round (k_grad_br_fold): Q row groups of 16 bytes per thread of a 1024-thread
+// workgroup hold a whole column; 0 when the problem is sparse or its columns are too long
+// for the registers (FP32: Q <= 5, m <= 20480; FP64: Q <= 3, m <= 6144).
+static int fused_q(const sca_problem* p) {
+  if (p->sparse) return 0;
+  const int64_t vn = 16 / (int64_t)p->esize;
+  const int64_t q = ((p->m + vn - 1) / vn + 1023) / 1024;
+  return q <= (p->esize == 4 ? kFusedMaxQ32 : kFusedMaxQ64) ? (int)q : 0;
+}
+
+// Workgroups (= fold partials) of the fused round: one per compute unit, at most 256
+// (k_part_reduce adds at most 16 partials per wave).
+static int fused_groups(const sca_problem* p) { return std::max(1, std::min(p->ncu, 256)); }
+
+// Largest column group whose registers fit (without spills) next to Q row groups of r and
+// of the partial (two buffers of C columns).
+static int fused_cmax(const sca_problem* p, int q) {
+  if (p->esize == 4) return q == 1 ? 8 : q == 2 ? 4 : q == 3 ? 2 : 1;
+  return q == 1 ? 4 : q == 2 ? 2 : 1;
+}
+
+// Takes launch shape l for problem p; false when p cannot run it.
+static bool take_launch(sca_problem* p, const sca_launch* l) {
+  int cols = l->grad_cols;
+  if (l->grad_kind == 4) {
+    const int q = fused_q(p);
+    if (q == 0) return false;
+    cols = std::min(cols, fused_cmax(p, q));
+  }
+  p->grad_kind = l->grad_kind;
+  p->grad_cols = cols;
+  p->grad_unroll = l->grad_unroll;
+  p->grad_wg_per_cu = l->grad_wg_per_cu;
+  return true;
 }
 
 static std::vector<sca_tune_entry> g_tuning;
@@ -127,13 +165,8 @@ extern "C" sca_status sca_tuning_set(const sca_tune_entry* e, int64_t count) {
 
 void sca::apply_tuning(sca_problem* p) {
   for (const sca_tune_entry& e : g_tuning) {
-    if (e.dtype == p->dtype && p->m >= e.m_lo && p->m <= e.m_hi) {
-      p->grad_kind = e.launch.grad_kind;
-      p->grad_cols = e.launch.grad_cols;
-      p->grad_unroll = e.launch.grad_unroll;
-      p->grad_wg_per_cu = e.launch.grad_wg_per_cu;
+    if (e.dtype == p->dtype && p->m >= e.m_lo && p->m <= e.m_hi && take_launch(p, &e.launch))
       return;
-    }
   }
 }
 
@@ -149,11 +182,8 @@ extern "C" sca_status sca_problem_get_launch(sca_problem* p, sca_launch* out) {
 
 extern "C" sca_status sca_problem_set_launch(sca_problem* p, const sca_launch* l) {
   if (!p) return set_error(SCA_EINVAL, "problem is NULL");
-  if (!launch_valid(l)) return set_error(SCA_EINVAL, "launch shape not available");
-  p->grad_kind = l->grad_kind;
-  p->grad_cols = l->grad_cols;
-  p->grad_unroll = l->grad_unroll;
-  p->grad_wg_per_cu = l->grad_wg_per_cu;
+  if (!launch_valid(l) || !take_launch(p, l))
+    return set_error(SCA_EINVAL, "launch shape not available for this problem");
   if (p->sgraph) {  // the solve graph bakes the launch shape in
     (void)hipGraphExecDestroy(p->sgraph);
     p->sgraph = nullptr;
@@ -210,7 +240,10 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
   ALLOC(p->d_J_idx, sizeof(int) * n);
   ALLOC(p->d_J_val, es * n);
   p->ldp = (p->m + 63) / 64 * 64;
-  ALLOC(p->d_part, p->sparse ? 64 : sizeof(double) * kMaxGroups * p->ldp);
+  // fold partials: kMaxGroups column groups (FP64 room) or one per workgroup of the fused round
+  ALLOC(p->d_part, p->sparse ? 64
+                             : std::max(sizeof(double) * kMaxGroups, es * fused_groups(p)) *
+                                   p->ldp);
   ALLOC(p->d_r64, sizeof(double) * p->ldp);
   ALLOC(p->d_rtmp, es * p->ldp);
   ALLOC(p->d_scal, sizeof(double) * 64);
@@ -453,7 +486,9 @@ static void grad_dense(sca_problem* p, T* x, const T* r, RoundState* st, const i
 #define GRAD_WW_LAUNCH(CC, UU)                                                              \
   hipLaunchKernelGGL((k_grad_br_wwalk<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,   \
                      (long long)p->lda, m, r, x, p->d_cn2, list, st, (T*)p->d_dx_sel, bp)
-  if (p->grad_kind == 3) {  // one wave per group of columns
+  if (p->grad_kind == 4) {  // rounds of the fused kind that run the two-pass kernels
+    GRAD_WG_LAUNCH(4, 4);
+  } else if (p->grad_kind == 3) {  // one wave per group of columns
     if (p->grad_cols == 4 && p->grad_unroll == 2)
       GRAD_WW_LAUNCH(4, 2);
     else if (p->grad_cols == 8 && p->grad_unroll == 1)
@@ -525,12 +560,60 @@ static void fold_dense(sca_problem* p, RoundState* st, const int* list, const T*
   prof_end(p, s, 0.0);
 }
 
+// S.2-S.5 fused (k_grad_br_fold, one workgroup per compute unit), then r += the partials.
+template <typename T>
+static void grad_fold_dense(sca_problem* p, T* x, T* r, const BRParams& bp, hipStream_t s) {
+  const int m = (int)p->m, G = fused_groups(p);
+  const int q = fused_q(p), c = p->grad_cols;
+  prof_begin(p, s, SCA_K_GRAD);
+#define FUSED(QQ, CC)                                                                       \
+  hipLaunchKernelGGL((k_grad_br_fold<T, QQ, CC>), dim3(G), dim3(1024), 0, s, (const T*)p->A, \
+                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols, p->d_state, \
+                     (T*)p->d_part, (long long)p->ldp, bp)
+  if constexpr (sizeof(T) == 4) {
+    switch (q * 16 + c) {
+      case 16 + 8: FUSED(1, 8); break;
+      case 16 + 4: FUSED(1, 4); break;
+      case 16 + 2: FUSED(1, 2); break;
+      case 16 + 1: FUSED(1, 1); break;
+      case 32 + 4: FUSED(2, 4); break;
+      case 32 + 2: FUSED(2, 2); break;
+      case 32 + 1: FUSED(2, 1); break;
+      case 48 + 2: FUSED(3, 2); break;
+      case 48 + 1: FUSED(3, 1); break;
+      case 64 + 1: FUSED(4, 1); break;
+      default: FUSED(5, 1); break;
+    }
+  } else {
+    switch (q * 16 + c) {
+      case 16 + 4: FUSED(1, 4); break;
+      case 16 + 2: FUSED(1, 2); break;
+      case 16 + 1: FUSED(1, 1); break;
+      case 32 + 2: FUSED(2, 2); break;
+      case 32 + 1: FUSED(2, 1); break;
+      default: FUSED(3, 1); break;
+    }
+  }
+#undef FUSED
+  prof_end(p, s, 0.0);
+  prof_begin(p, s, SCA_K_FOLD);
+  constexpr int VN = V16<T>::N;
+  const int nq = (m + VN - 1) / VN;
+  hipLaunchKernelGGL(k_part_reduce<T>, dim3((nq + 63) / 64), dim3(1024), 0, s,
+                     (const T*)p->d_part, (long long)p->ldp, G, m, r);
+  prof_end(p, s, 0.0);
+}
+
 template <typename T>
 static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
                                uint64_t Tthr, const BRParams& bp) {
   prof_begin(p, s, SCA_K_SELECT);
   launch_select(p, o, Tthr, s);
   prof_end(p, s, 0.0);
+  if (p->grad_kind == 4) {
+    grad_fold_dense<T>(p, x, r, bp, s);
+    return;
+  }
   prof_begin(p, s, SCA_K_GRAD);
   grad_dense<T>(p, x, r, p->d_state, p->d_sel_cols, bp, s);
   prof_end(p, s, 0.0);

@@ -587,6 +587,189 @@ k_grad_br_wwalk(const T* __restrict__ A, long long lda, int m, const T* __restri
   }
 }
 
+// ------------------------------------------------------------------ fused round (dense)
+// S.2-S.5 in one pass over the drawn columns, for columns that fit one 1024-thread
+// workgroup: thread t owns the 16-byte row groups t, t + 1024, ..., t + (Q-1)*1024 and keeps
+// those rows of r and of its workgroup's fold partial in registers.  Workgroup w takes the
+// drawn coordinates [w*S/G, (w+1)*S/G) in groups of C; per group it forms the C gradients
+// (wave butterflies, then the 16 wave sums in a fixed order), the best responses and the
+// moves, and adds move * column into the partial from the registers that hold the column,
+// so A_S is read once per round.  The next group's loads are issued before the current
+// group's reduction.  part[w] receives workgroup w's partial (k_part_reduce adds them to r);
+// st->moved_updates counts the moved coordinates.
+constexpr int kFusedMaxQ32 = 5;  // row groups per thread (registers), FP32
+constexpr int kFusedMaxQ64 = 3;  // and FP64
+
+template <typename T, int Q, int C>
+__global__ void __launch_bounds__(1024)
+k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
+               T* __restrict__ x, const double* __restrict__ cn2,
+               const int* __restrict__ sel_cols, RoundState* __restrict__ st,
+               T* __restrict__ part, long long ldp, BRParams bp) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  __shared__ T red[2][C][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = st->S_cnt;
+  const T gamma = (T)st->gamma_cur;
+  const int G = gridDim.x;
+  const int t0 = (int)((long long)S * blockIdx.x / G);
+  const int t1 = (int)((long long)S * (blockIdx.x + 1) / G);
+  const int nq = (m + VN - 1) / VN;  // row groups holding rows < m (lda covers them)
+  // The last slot is the only one that can reach past row m: its loads use a clamped row
+  // group and its rows >= m are zeroed (A's padding rows may hold anything).
+  const int glast = min((Q - 1) * 1024 + tid, nq - 1);
+  const int rlast = ((Q - 1) * 1024 + tid) * VN;
+  const int nlast = max(0, min(VN, m - rlast));  // valid rows of the last slot
+  VA rr[Q], pa[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int row = (q * 1024 + tid) * VN;
+    if (row + VN <= m) {
+      rr[q] = *reinterpret_cast<const VA*>(r + row);
+    } else {
+#pragma unroll
+      for (int e = 0; e < VN; ++e) rr[q][e] = row + e < m ? r[row + e] : (T)0;
+    }
+#pragma unroll
+    for (int e = 0; e < VN; ++e) pa[q][e] = (T)0;
+  }
+  const int nitems = (t1 - t0 + C - 1) / C;
+  VA a[C][Q];
+  int jc[C];
+  T xj[C];
+  double q2[C];
+  auto load_group = [&](int tb, VA (&dst)[C][Q], int (&jd)[C], T (&xd)[C], double (&qd)[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      jd[c] = sel_cols[min(tb + c, t1 - 1)];  // a short last group repeats its last column
+      const T* col = A + (size_t)jd[c] * lda;
+#pragma unroll
+      for (int q = 0; q < Q - 1; ++q)
+        dst[c][q] = __builtin_nontemporal_load(
+            reinterpret_cast<const VA*>(col + (q * 1024 + tid) * VN));
+      dst[c][Q - 1] = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col + glast * VN));
+      xd[c] = x[jd[c]];
+      qd[c] = cn2[jd[c]];
+    }
+  };
+  if (nitems > 0) load_group(t0, a, jc, xj, q2);
+  long long moved = 0;
+  for (int it = 0; it < nitems; ++it) {
+    const int tb = t0 + it * C;
+    VA an[C][Q];
+    int jn[C];
+    T xn[C];
+    double qn[C];
+    if (it + 1 < nitems) load_group(tb + C, an, jn, xn, qn);
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (nlast < VN) {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) a[c][Q - 1][e] = e < nlast ? a[c][Q - 1][e] : (T)0;
+      }
+      acc[c] = (T)0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) acc[c] += a[c][q][e] * rr[q][e];
+    }
+    const int buf = it & 1;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const T v = wave_sum(acc[c]);
+      if (lane == 0) red[buf][c][wave] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (tb + c < t1) {
+        const T* rs = red[buf][c];
+        const T dot = (((rs[0] + rs[1]) + (rs[2] + rs[3])) + ((rs[4] + rs[5]) + (rs[6] + rs[7]))) +
+                      (((rs[8] + rs[9]) + (rs[10] + rs[11])) +
+                       ((rs[12] + rs[13]) + (rs[14] + rs[15])));
+        T g = dot - (T)bp.c2 * xj[c];
+        if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj[c], bp);
+        const T qq = (T)(q2[c] + bp.tau);
+        const T xh = soft_clip<T>(xj[c] - g / qq, (T)bp.lam_eta / qq, (T)bp.beta);
+        const T d = gamma * (xh - xj[c]);
+        if (d != (T)0) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int e = 0; e < VN; ++e) pa[q][e] += a[c][q][e] * d;
+          ++moved;
+        }
+        if (tid == 0) x[jc[c]] = xj[c] + d;
+      }
+    }
+    if (it + 1 < nitems) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) a[c][q] = an[c][q];
+        jc[c] = jn[c];
+        xj[c] = xn[c];
+        q2[c] = qn[c];
+      }
+    }
+  }
+  T* dst = part + (size_t)blockIdx.x * ldp;
+#pragma unroll
+  for (int q = 0; q < Q - 1; ++q)
+    *reinterpret_cast<VA*>(dst + (q * 1024 + tid) * VN) = pa[q];
+  if ((Q - 1) * 1024 + tid < nq) *reinterpret_cast<VA*>(dst + rlast) = pa[Q - 1];
+  if (tid == 0) {
+    if (moved) atomicAdd(reinterpret_cast<unsigned long long*>(&st->moved_updates),
+                         (unsigned long long)moved);
+    if (blockIdx.x == 0) st->ngroups = G;
+  }
+}
+
+// r[i] += sum over w < G of part[w][i]: each lane one 16-byte row group, wave v adds the
+// partials [v*G/16, (v+1)*G/16) in order, then the 16 wave sums are added to r in wave order.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, T* __restrict__ r) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  constexpr int KMAX = 16;  // partials per wave (G <= 256)
+  __shared__ VA sh[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = (blockIdx.x * 64 + lane) * VN;
+  VA acc;
+#pragma unroll
+  for (int e = 0; e < VN; ++e) acc[e] = (T)0;
+  const int g0 = wave * G / 16, g1 = (wave + 1) * G / 16;
+  if (row < m && g1 > g0) {
+    VA v[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      v[k] = *reinterpret_cast<const VA*>(part + (size_t)min(g0 + k, g1 - 1) * ldp + row);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (g0 + k < g1) acc += v[k];
+  }
+  sh[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && row < m) {
+    if (row + VN <= m) {
+      VA s = *reinterpret_cast<const VA*>(r + row);
+#pragma unroll
+      for (int w = 0; w < 16; ++w) s += sh[w][lane];
+      *reinterpret_cast<VA*>(r + row) = s;
+    } else {
+      for (int e = 0; e < m - row; ++e) {
+        T s = r[row + e];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) s += sh[w][lane][e];
+        r[row + e] = s;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ compaction
 // Two passes over v[0..N): per-chunk nonzero counts, then an ordered scatter of
 // (index, value) for the nonzero entries.  N is read from device memory.
