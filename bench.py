@@ -439,7 +439,8 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         vals = load(d, counter)
         copy = [v for k, v in vals.items() if "k_stream_copy" in k][0]
-        grad = [v for k, v in vals.items() if "k_grad_br" in k and "<float" in k][0]
+        want = grad_kernel_name(probe["launch"], False, probe["m"])
+        grad = [v for k, v in vals.items() if want in k.replace(" ", "")][0]
         cal = CALIB_BYTES / (sorted(copy)[len(copy) // 2] * 1024.0)
         res[counter] = dict(copy_kib=sorted(copy)[len(copy) // 2], scale=cal,
                             grad_kib_mean=sum(grad) / len(grad), launches=len(grad))

@@ -595,10 +595,22 @@ k_grad_br_wwalk(const T* __restrict__ A, long long lda, int m, const T* __restri
 // (wave butterflies, then the 16 wave sums in a fixed order), the best responses and the
 // moves, and adds move * column into the partial from the registers that hold the column,
 // so A_S is read once per round.  The next group's loads are issued before the current
-// group's reduction.  part[w] receives workgroup w's partial (k_part_reduce adds them to r);
+// group is reduced, so one group is in flight at a time (keeping two in flight measured
+// slower for 80 KB columns, and no faster for shorter ones).  Loads are never skipped
+// (past the end of the share, or in a short last group, every lane reads the first 16
+// bytes of A instead), which keeps the compiler's wait counts exact.
+// part[w] receives workgroup w's partial (k_part_reduce adds them to r);
 // st->moved_updates counts the moved coordinates.
 constexpr int kFusedMaxQ32 = 5;  // row groups per thread (registers), FP32
 constexpr int kFusedMaxQ64 = 3;  // and FP64
+
+template <typename T, int Q, int C>
+struct FusedBuf {
+  typename V16<T>::v a[C][Q];
+  int j[C];
+  T x[C];
+  double q2[C];
+};
 
 template <typename T, int Q, int C>
 __global__ void __launch_bounds__(1024)
@@ -616,9 +628,13 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
   const int t0 = (int)((long long)S * blockIdx.x / G);
   const int t1 = (int)((long long)S * (blockIdx.x + 1) / G);
   const int nq = (m + VN - 1) / VN;  // row groups holding rows < m (lda covers them)
-  // The last slot is the only one that can reach past row m: its loads use a clamped row
-  // group and its rows >= m are zeroed (A's padding rows may hold anything).
-  const int glast = min((Q - 1) * 1024 + tid, nq - 1);
+  // Byte offsets of the owned row groups within a column.  The last slot is the only one
+  // that can reach past row m: it is clamped to the last row group, and its rows >= m are
+  // zeroed after each load (A's padding rows may hold anything).
+  uint32_t boff[Q];
+#pragma unroll
+  for (int q = 0; q < Q - 1; ++q) boff[q] = (uint32_t)((q * 1024 + tid) * 16);
+  boff[Q - 1] = (uint32_t)(min((Q - 1) * 1024 + tid, nq - 1) * 16);
   const int rlast = ((Q - 1) * 1024 + tid) * VN;
   const int nlast = max(0, min(VN, m - rlast));  // valid rows of the last slot
   VA rr[Q], pa[Q];
@@ -635,47 +651,36 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
     for (int e = 0; e < VN; ++e) pa[q][e] = (T)0;
   }
   const int nitems = (t1 - t0 + C - 1) / C;
-  VA a[C][Q];
-  int jc[C];
-  T xj[C];
-  double q2[C];
-  auto load_group = [&](int tb, VA (&dst)[C][Q], int (&jd)[C], T (&xd)[C], double (&qd)[C]) {
+  long long moved = 0;
+  auto load = [&](int tb, FusedBuf<T, Q, C>& B) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      jd[c] = sel_cols[min(tb + c, t1 - 1)];  // a short last group repeats its last column
-      const T* col = A + (size_t)jd[c] * lda;
+      const bool ok = tb + c < t1;  // uniform
+      const uint32_t omask = ok ? 0xffffffffu : 0u;
+      B.j[c] = ok ? sel_cols[tb + c] : 0;
+      const char* col = reinterpret_cast<const char*>(A + (size_t)B.j[c] * lda);
 #pragma unroll
-      for (int q = 0; q < Q - 1; ++q)
-        dst[c][q] = __builtin_nontemporal_load(
-            reinterpret_cast<const VA*>(col + (q * 1024 + tid) * VN));
-      dst[c][Q - 1] = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col + glast * VN));
-      xd[c] = x[jd[c]];
-      qd[c] = cn2[jd[c]];
+      for (int q = 0; q < Q; ++q)
+        B.a[c][q] = __builtin_nontemporal_load(
+            reinterpret_cast<const VA*>(col + (boff[q] & omask)));
+      B.x[c] = x[B.j[c]];
+      B.q2[c] = cn2[B.j[c]];
     }
   };
-  if (nitems > 0) load_group(t0, a, jc, xj, q2);
-  long long moved = 0;
-  for (int it = 0; it < nitems; ++it) {
-    const int tb = t0 + it * C;
-    VA an[C][Q];
-    int jn[C];
-    T xn[C];
-    double qn[C];
-    if (it + 1 < nitems) load_group(tb + C, an, jn, xn, qn);
+  auto process = [&](int tb, FusedBuf<T, Q, C>& B, int buf) {
     T acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (nlast < VN) {
 #pragma unroll
-        for (int e = 0; e < VN; ++e) a[c][Q - 1][e] = e < nlast ? a[c][Q - 1][e] : (T)0;
+        for (int e = 0; e < VN; ++e) B.a[c][Q - 1][e] = e < nlast ? B.a[c][Q - 1][e] : (T)0;
       }
       acc[c] = (T)0;
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int e = 0; e < VN; ++e) acc[c] += a[c][q][e] * rr[q][e];
+        for (int e = 0; e < VN; ++e) acc[c] += B.a[c][q][e] * rr[q][e];
     }
-    const int buf = it & 1;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const T v = wave_sum(acc[c]);
@@ -689,30 +694,30 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
         const T dot = (((rs[0] + rs[1]) + (rs[2] + rs[3])) + ((rs[4] + rs[5]) + (rs[6] + rs[7]))) +
                       (((rs[8] + rs[9]) + (rs[10] + rs[11])) +
                        ((rs[12] + rs[13]) + (rs[14] + rs[15])));
-        T g = dot - (T)bp.c2 * xj[c];
-        if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj[c], bp);
-        const T qq = (T)(q2[c] + bp.tau);
-        const T xh = soft_clip<T>(xj[c] - g / qq, (T)bp.lam_eta / qq, (T)bp.beta);
-        const T d = gamma * (xh - xj[c]);
+        const T xj = B.x[c];
+        T g = dot - (T)bp.c2 * xj;
+        if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+        const T qq = (T)(B.q2[c] + bp.tau);
+        const T xh = soft_clip<T>(xj - g / qq, (T)bp.lam_eta / qq, (T)bp.beta);
+        const T d = gamma * (xh - xj);
         if (d != (T)0) {
 #pragma unroll
           for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int e = 0; e < VN; ++e) pa[q][e] += a[c][q][e] * d;
+            for (int e = 0; e < VN; ++e) pa[q][e] += B.a[c][q][e] * d;
           ++moved;
         }
-        if (tid == 0) x[jc[c]] = xj[c] + d;
+        if (tid == 0) x[B.j[c]] = xj + d;
       }
     }
-    if (it + 1 < nitems) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) a[c][q] = an[c][q];
-        jc[c] = jn[c];
-        xj[c] = xn[c];
-        q2[c] = qn[c];
-      }
+  };
+  if (nitems > 0) {
+    FusedBuf<T, Q, C> B0, B1;
+    load(t0, B0);
+    for (int it = 0; it < nitems; ++it) {
+      load(t0 + (it + 1) * C, B1);
+      process(t0 + it * C, B0, it & 1);
+      B0 = B1;
     }
   }
   T* dst = part + (size_t)blockIdx.x * ldp;
