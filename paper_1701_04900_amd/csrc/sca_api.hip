@@ -560,16 +560,25 @@ static void fold_dense(sca_problem* p, RoundState* st, const int* list, const T*
   prof_end(p, s, 0.0);
 }
 
-// S.2-S.5 fused (k_grad_br_fold, one workgroup per compute unit), then r += the partials.
+// The fused round draws the blocks itself when every thread of a workgroup handles at most
+// 32 blocks and a workgroup's share of the drawn list fits its LDS list.
+static bool fused_draws(const sca_problem* p) {
+  const int64_t G = fused_groups(p);
+  return p->nblocks <= kFusedSelBlocks && (p->n + G - 1) / G <= kFusedSelCols;
+}
+
+// S.1-S.5 fused (k_grad_br_fold, one workgroup per compute unit, S.1 inside when
+// fs.on), then r += the partials (and the round state advanced when S.1 ran inside).
 template <typename T>
-static void grad_fold_dense(sca_problem* p, T* x, T* r, const BRParams& bp, hipStream_t s) {
+static void grad_fold_dense(sca_problem* p, T* x, T* r, const BRParams& bp, const FusedSel& fs,
+                            hipStream_t s) {
   const int m = (int)p->m, G = fused_groups(p);
   const int q = fused_q(p), c = p->grad_cols;
   prof_begin(p, s, SCA_K_GRAD);
 #define FUSED(QQ, CC)                                                                       \
   hipLaunchKernelGGL((k_grad_br_fold<T, QQ, CC>), dim3(G), dim3(1024), 0, s, (const T*)p->A, \
                      (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols, p->d_state, \
-                     (T*)p->d_part, (long long)p->ldp, bp)
+                     (T*)p->d_part, (long long)p->ldp, bp, fs)
   if constexpr (sizeof(T) == 4) {
     switch (q * 16 + c) {
       case 16 + 8: FUSED(1, 8); break;
@@ -600,18 +609,24 @@ static void grad_fold_dense(sca_problem* p, T* x, T* r, const BRParams& bp, hipS
   constexpr int VN = V16<T>::N;
   const int nq = (m + VN - 1) / VN;
   hipLaunchKernelGGL(k_part_reduce<T>, dim3((nq + 63) / 64), dim3(1024), 0, s,
-                     (const T*)p->d_part, (long long)p->ldp, G, m, r);
+                     (const T*)p->d_part, (long long)p->ldp, G, m, r, p->d_state, fs.on);
   prof_end(p, s, 0.0);
 }
 
 template <typename T>
 static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
                                uint64_t Tthr, const BRParams& bp) {
+  FusedSel fs{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
+  if (p->grad_kind == 4 && fused_draws(p)) {
+    fs.on = 1;
+    grad_fold_dense<T>(p, x, r, bp, fs, s);
+    return;
+  }
   prof_begin(p, s, SCA_K_SELECT);
   launch_select(p, o, Tthr, s);
   prof_end(p, s, 0.0);
   if (p->grad_kind == 4) {
-    grad_fold_dense<T>(p, x, r, bp, s);
+    grad_fold_dense<T>(p, x, r, bp, fs, s);
     return;
   }
   prof_begin(p, s, SCA_K_GRAD);

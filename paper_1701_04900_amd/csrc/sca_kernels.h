@@ -603,6 +603,18 @@ k_grad_br_wwalk(const T* __restrict__ A, long long lda, int m, const T* __restri
 // st->moved_updates counts the moved coordinates.
 constexpr int kFusedMaxQ32 = 5;  // row groups per thread (registers), FP32
 constexpr int kFusedMaxQ64 = 3;  // and FP64
+constexpr int kFusedSelCols = 4096;     // LDS list of a workgroup's share (draw in the kernel)
+constexpr int kFusedSelBlocks = 32768;  // blocks drawn in the kernel (32 per thread at most)
+
+// Block draw of the fused round (on = 0: the drawn list comes from k_select).
+struct FusedSel {
+  const int* bp;  // block pointer (nblocks + 1)
+  int nblocks;
+  int on;
+  uint64_t seed;
+  uint64_t T;
+  uint32_t inst;
+};
 
 template <typename T, int Q, int C>
 struct FusedBuf {
@@ -617,16 +629,14 @@ __global__ void __launch_bounds__(1024)
 k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
                T* __restrict__ x, const double* __restrict__ cn2,
                const int* __restrict__ sel_cols, RoundState* __restrict__ st,
-               T* __restrict__ part, long long ldp, BRParams bp) {
+               T* __restrict__ part, long long ldp, BRParams bp, FusedSel fs) {
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
   __shared__ T red[2][C][16];
+  __shared__ int s_scan[17];
+  __shared__ int s_cols[kFusedSelCols];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int S = st->S_cnt;
-  const T gamma = (T)st->gamma_cur;
   const int G = gridDim.x;
-  const int t0 = (int)((long long)S * blockIdx.x / G);
-  const int t1 = (int)((long long)S * (blockIdx.x + 1) / G);
   const int nq = (m + VN - 1) / VN;  // row groups holding rows < m (lda covers them)
   // Byte offsets of the owned row groups within a column.  The last slot is the only one
   // that can reach past row m: it is clamped to the last row group, and its rows >= m are
@@ -650,6 +660,44 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
 #pragma unroll
     for (int e = 0; e < VN; ++e) pa[q][e] = (T)0;
   }
+  // S.1, here or in k_select.  Here (fs.on): every workgroup evaluates the draw of every
+  // block (the k_select draw, round st->k), scans the drawn columns in block order and lists
+  // its own share [t0, t1) in LDS; the round state is advanced afterwards by k_part_reduce,
+  // so this round's step is st->gamma_next.
+  int S;
+  T gamma;
+  if (fs.on) {
+    const long long k = st->k;
+    gamma = (T)st->gamma_next;
+    const int per = (fs.nblocks + 1023) / 1024;  // <= 32 (host check)
+    const int b0 = min(fs.nblocks, tid * per), b1 = min(fs.nblocks, b0 + per);
+    int cnt = 0;
+    uint32_t mask = 0;
+    for (int i = b0; i < b1; ++i) {
+      if (block_drawn((uint32_t)i, (uint64_t)k, fs.inst, fs.seed, fs.T)) {
+        cnt += fs.bp[i + 1] - fs.bp[i];
+        mask |= 1u << (i - b0);
+      }
+    }
+    int off = block_exclusive_scan_1024(cnt, s_scan, &S);
+    const int u0 = (int)((long long)S * blockIdx.x / G);
+    const int u1 = (int)((long long)S * (blockIdx.x + 1) / G);
+    for (int i = b0; i < b1; ++i) {
+      if (mask & (1u << (i - b0))) {
+        const int c0 = fs.bp[i], len = fs.bp[i + 1] - c0;
+        const int lo = max(off, u0), hi = min(off + len, u1);
+        for (int t = lo; t < hi; ++t) s_cols[t - u0] = c0 + (t - off);
+        off += len;
+      }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && tid == 0) st->S_cnt = S;
+  } else {
+    S = st->S_cnt;
+    gamma = (T)st->gamma_cur;
+  }
+  const int t0 = (int)((long long)S * blockIdx.x / G);
+  const int t1 = (int)((long long)S * (blockIdx.x + 1) / G);
   const int nitems = (t1 - t0 + C - 1) / C;
   long long moved = 0;
   auto load = [&](int tb, FusedBuf<T, Q, C>& B) {
@@ -657,7 +705,7 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
     for (int c = 0; c < C; ++c) {
       const bool ok = tb + c < t1;  // uniform
       const uint32_t omask = ok ? 0xffffffffu : 0u;
-      B.j[c] = ok ? sel_cols[tb + c] : 0;
+      B.j[c] = ok ? (fs.on ? s_cols[tb + c - t0] : sel_cols[tb + c]) : 0;
       const char* col = reinterpret_cast<const char*>(A + (size_t)B.j[c] * lda);
 #pragma unroll
       for (int q = 0; q < Q; ++q)
@@ -734,9 +782,20 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
 
 // r[i] += sum over w < G of part[w][i]: each lane one 16-byte row group, wave v adds the
 // partials [v*G/16, (v+1)*G/16) in order, then the 16 wave sums are added to r in wave order.
+// With advance != 0 (the block draw ran inside the fused kernel) it also advances the round
+// state the way k_select does: next round, step, drawn-coordinate total.
 template <typename T>
 __global__ void __launch_bounds__(1024)
-k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, T* __restrict__ r) {
+k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, T* __restrict__ r,
+              RoundState* __restrict__ st, int advance) {
+  if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double g = st->gamma_next;
+    st->coord_updates += st->S_cnt;
+    st->work_ctr = 0;
+    st->k += 1;
+    st->gamma_cur = g;
+    st->gamma_next = g * (1.0 - st->gamma_mu * g);
+  }
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
   constexpr int KMAX = 16;  // partials per wave (G <= 256)

@@ -100,6 +100,19 @@ def test_fused_fp64_matches_oracle(m, n, block, p, cols):
         assert _rel(rg, ro) <= 1e-10, (i, _rel(rg, ro))
 
 
+def test_fused_with_separate_block_draw_fp64():
+    """More blocks than the in-kernel draw takes (40000 scalar blocks > 32768): the drawn
+    list comes from the separate selection kernel, the fused kernel does S.2-S.5."""
+    w = inputs.dense_problem(300, 40000, nnz_frac=0.01, lam_frac=0.02, block=1, p=0.05,
+                             dtype=torch.float64, seed=31)
+    assert len(w.block_ptr) - 1 == 40000
+    prob = _oracle(w)
+    run = Run(w, cols=4)
+    for xo, ro in _trajectory(w, prob, 12, 4):
+        xg, rg = run.step(4)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+
+
 def test_fused_moved_count_matches_oracle_fp64():
     w = inputs.dense_problem(1201, 3000, nnz_frac=0.02, lam_frac=0.02, block=16, p=0.5,
                              dtype=torch.float64, seed=21)
