@@ -311,7 +311,9 @@ sca_status sca_batch_step(sca_batch* batch, const sca_opts* opts, int64_t round_
  * (F - F_star)/|F_star| <= tol_rel_obj and (when tol_merit > 0, at the cost of a full
  * pass over every A) ||xh(x) - x||_inf <= tol_merit; a converged instance stops drawing
  * blocks.  stats
- * (count entries, may be NULL) receive per-instance results.  Synchronises 'stream';
+ * (count entries, may be NULL) receive per-instance results (coord_updates per instance;
+ * moved_updates is the batch-wide total of moved coordinates, the same in every entry).
+ * Synchronises 'stream';
  * returns SCA_ENOTCONV when an instance ran out of max_rounds. */
 sca_status sca_batch_solve(sca_batch* batch, const sca_opts* opts, void* x_all_dev,
                            sca_stats* stats_host, void* stream);

@@ -1061,10 +1061,13 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
       SCA_OK)
     return st;
   std::vector<long long> done(B->K), upd(B->K);
+  long long moved_all = 0;
   if (hipMemcpy(done.data(), B->d_done, sizeof(long long) * B->K, hipMemcpyDeviceToHost) !=
           hipSuccess ||
       hipMemcpy(upd.data(), B->d_upd, sizeof(long long) * B->K, hipMemcpyDeviceToHost) !=
-          hipSuccess)
+          hipSuccess ||
+      hipMemcpy(&moved_all, (char*)B->d_state + offsetof(RoundState, moved_updates),
+                sizeof(long long), hipMemcpyDeviceToHost) != hipSuccess)
     return set_error(SCA_EHIP, "batch stats copy failed");
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int notconv = 0;
@@ -1077,7 +1080,7 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
       sca_stats& S = stats[q];
       S.rounds = conv ? done[q] : k;
       S.coord_updates = upd[q];
-      S.moved_updates = 0;
+      S.moved_updates = moved_all;
       S.F = F[q];
       S.merit = mer[q];
       S.MF = mf[q];
