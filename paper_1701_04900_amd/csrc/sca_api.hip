@@ -231,6 +231,7 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
   ALLOC(p->d_cn2, sizeof(double) * n);
   ALLOC(p->d_state, sizeof(RoundState));
   ALLOC(p->d_sel_cols, sizeof(int) * n);
+  ALLOC(p->d_blk_list, sizeof(int2) * (kSelList + 1));
   ALLOC(p->d_dx_sel, es * n);
   ALLOC(p->d_mbstate, sizeof(RoundState));
   ALLOC(p->d_mbcols, sizeof(int) * n);
@@ -266,6 +267,7 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
 
 void sca::free_workspace(sca_problem* p) {
   void* ptrs[] = {p->d_bp, p->d_cn2, p->d_state, p->d_mbstate, p->d_mbcols, p->d_ring,
+                  p->d_blk_list,
                   p->d_sel_cols, p->d_dx_sel, p->d_chunk_cnt,
                   p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
                   p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
@@ -463,9 +465,18 @@ extern "C" sca_status sca_profile_get(sca_problem* p, double* ms, int64_t* launc
 
 // ------------------------------------------------------------------ launch sequences
 // S.1: the block draw of the round in flight (see k_select).
+// When many columns are expected per round the single-workgroup draw only lists the drawn
+// blocks and k_select_expand writes their columns with the whole grid.
 void sca::launch_select(sca_problem* p, const sca_opts* o, uint64_t Tthr, hipStream_t s) {
+  const double expect = std::min(1.0, o->select_p) * (double)p->n;
+  int2* blk = expect >= (double)kSelExpandCols ? (int2*)p->d_blk_list : nullptr;
   hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)p->nblocks, p->d_bp, o->seed,
-                     o->instance, Tthr, p->d_state, p->d_sel_cols);
+                     o->instance, Tthr, p->d_state, p->d_sel_cols, blk);
+  if (blk) {
+    const int g = std::max(1, std::min(p->ncu, (int)((p->nblocks + 3) / 4)));
+    hipLaunchKernelGGL(k_select_expand, dim3(g), dim3(256), 0, s, (const int2*)blk, p->d_bp,
+                       p->d_sel_cols);
+  }
 }
 
 // S.2-S.4 on the coordinates listed in 'list' (count and step in *st), reading r.

@@ -49,6 +49,7 @@ struct sca_problem {
   double* d_cn2 = nullptr;
   sca::RoundState* d_state = nullptr;
   int* d_sel_cols = nullptr;
+  void* d_blk_list = nullptr;  // drawn blocks and list positions (kSelList + 1 int2)
   void* d_dx_sel = nullptr;
   int* d_chunk_cnt = nullptr;
   int* d_J_idx = nullptr;

@@ -162,13 +162,14 @@ static __global__ void k_init_state(RoundState* st, long long k, double gamma, d
 // gradient work counter.  (A grid of workgroups with a last-arriver listing measured slower
 // here: its device-scope fences cost more than the draws they spread.)
 constexpr int kSelList = 4096;
+constexpr int kSelExpandCols = 16384;  // expected drawn columns from which the grid expands
 constexpr int kSelBp = 4096;  // block pointers staged in LDS when nblocks < kSelBp
 
 template <typename BP>
 __device__ __forceinline__ void select_run(int nblocks, BP bp, uint64_t seed, uint32_t inst,
                                            uint64_t T, RoundState* __restrict__ st,
                                            int* __restrict__ sel_cols, int* sh, int* s_blk,
-                                           int* s_off) {
+                                           int* s_off, int2* __restrict__ blk_out) {
   const long long k = st->k;
   double g_next = 0.0, g_mu = 0.0;
   long long upd = 0;
@@ -203,11 +204,17 @@ __device__ __forceinline__ void select_run(int nblocks, BP bp, uint64_t seed, ui
       }
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q = wave; q < nsel_total; q += 16) {
-      const int i = s_blk[q], o = s_off[q];
-      const int c0 = bp[i], len = bp[i + 1] - c0;
-      for (int c = lane; c < len; c += 64) sel_cols[o + c] = c0 + c;
+    if (blk_out) {  // k_select_expand writes the columns with the whole grid
+      for (int q = threadIdx.x; q < nsel_total; q += 1024)
+        blk_out[q] = make_int2(s_blk[q], s_off[q]);
+      if (threadIdx.x == 0) blk_out[kSelList].x = nsel_total;
+    } else {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      for (int q = wave; q < nsel_total; q += 16) {
+        const int i = s_blk[q], o = s_off[q];
+        const int c0 = bp[i], len = bp[i + 1] - c0;
+        for (int c = lane; c < len; c += 64) sel_cols[o + c] = c0 + c;
+      }
     }
   } else {
     for (int i = b0; i < b1; ++i) {
@@ -215,6 +222,7 @@ __device__ __forceinline__ void select_run(int nblocks, BP bp, uint64_t seed, ui
         for (int c = bp[i]; c < bp[i + 1]; ++c) sel_cols[off++] = c;
       }
     }
+    if (blk_out && threadIdx.x == 0) blk_out[kSelList].x = 0;  // nothing left to expand
   }
   if (threadIdx.x == 0) {
     st->S_cnt = total;
@@ -226,10 +234,14 @@ __device__ __forceinline__ void select_run(int nblocks, BP bp, uint64_t seed, ui
   }
 }
 
+// blk_out (may be NULL): when given and the drawn blocks fit the shared list, the drawn
+// blocks and their first list positions go to blk_out[0..nsel) and nsel to
+// blk_out[kSelList].x instead of the columns (k_select_expand writes those).
 static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* __restrict__ bp,
                                                         uint64_t seed, uint32_t inst, uint64_t T,
                                                         RoundState* __restrict__ st,
-                                                        int* __restrict__ sel_cols) {
+                                                        int* __restrict__ sel_cols,
+                                                        int2* __restrict__ blk_out) {
   __shared__ int sh[17];
   __shared__ int s_blk[kSelList];
   __shared__ int s_off[kSelList];
@@ -237,9 +249,25 @@ static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* 
   if (nblocks < kSelBp) {
     for (int i = threadIdx.x; i <= nblocks; i += 1024) s_bp[i] = bp[i];
     __syncthreads();
-    select_run(nblocks, (const int*)s_bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off);
+    select_run(nblocks, (const int*)s_bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off,
+               blk_out);
   } else {
-    select_run(nblocks, bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off);
+    select_run(nblocks, bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off, blk_out);
+  }
+}
+
+// The columns of the blocks listed by k_select in blk (count in blk[kSelList].x): wave v of
+// workgroup g takes listed blocks 4g + v, 4g + v + 4G, ... and writes their columns at
+// their list positions with coalesced stores.
+static __global__ void __launch_bounds__(256) k_select_expand(const int2* __restrict__ blk,
+                                                              const int* __restrict__ bp,
+                                                              int* __restrict__ sel_cols) {
+  const int n = blk[kSelList].x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = blockIdx.x * 4 + wave; q < n; q += gridDim.x * 4) {
+    const int2 e = blk[q];
+    const int c0 = bp[e.x], len = bp[e.x + 1] - c0;
+    for (int c = lane; c < len; c += 64) sel_cols[e.y + c] = c0 + c;
   }
 }
 

@@ -675,7 +675,7 @@ void mround(sca_multi* M, const sca_opts* o, T* X, T* R, hipStream_t s, uint64_t
   int* S_ptr = (int*)((char*)M->d_state + offsetof(RoundState, S_cnt));
   mprof_begin(M, s, SCA_K_SELECT);
   hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, (int)M->nblocks, M->d_bp, o->seed,
-                     o->instance, Tthr, M->d_state, M->d_sel);
+                     o->instance, Tthr, M->d_state, M->d_sel, (int2*)nullptr);
   mprof_end(M, s);
   mprof_begin(M, s, SCA_K_GRAD);
   launch_mgrad<T, T>(M, R, (long long)M->lda, M->d_sel, S_ptr, (T*)M->d_G, s);

@@ -6,7 +6,9 @@
 * one row, one column, a single block holding every coordinate;
 * orthonormal columns with tau = 0 and gamma = 1: one round is the soft-threshold of A^T b
   (closed form), and it is a fixed point;
-* a box bound that most coordinates hit (nonconvex c > 0).
+* a box bound that most coordinates hit (nonconvex c > 0);
+* about 20000 drawn columns per round (the drawn list written by the whole grid), dense
+  and sparse, and more drawn blocks than the selection's shared list holds.
 
 FP64 tolerance 1e-10 relative, as for the other dense tests."""
 import math
@@ -134,3 +136,35 @@ def test_box_bound_hit_by_most_coordinates(kind):
     assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
     assert np.max(np.abs(xg)) <= 0.05
     assert np.mean(np.abs(np.abs(xg) - 0.05) < 1e-12) > 0.3  # most drawn coordinates at the box
+
+
+@pytest.mark.parametrize("block,p", [(32, 0.6), (1, 0.5)])
+def test_long_drawn_lists_two_pass(block, p):
+    """About 20000 drawn columns per round: the draw lists the drawn blocks and a grid-wide
+    kernel writes their columns (block 32), or, with more drawn blocks than the shared list
+    holds (scalar blocks), the draw writes the columns itself."""
+    w = inputs.dense_problem(64, 40000, nnz_frac=0.01, lam_frac=0.02, block=block, p=p,
+                             dtype=torch.float64, seed=46)
+    prob = _oracle(w)
+    run = Run(w, "two_pass")
+    for k0 in range(0, 9, 3):
+        xg, rg = run.step(3)
+        xo, ro, _ = _oracle_rounds(w, prob, k0 + 3)
+        assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10, k0
+
+
+def test_long_drawn_list_sparse():
+    w = inputs.sparse_problem(600, 40000, per_col=6, nnz_frac=0.01, lam_frac=0.02, block=64,
+                              p=0.5, dtype=torch.float64, seed=47)
+    prob = O.Problem(A=w.scipy_csr().tocsc(), b=w.b.double().cpu().numpy(), lam=w.lam, c=w.c,
+                     beta=w.beta, block_ptr=w.block_ptr)
+    wd = w.to("cuda")
+    P = sca.Problem.from_workload(wd)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+    x = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    r = torch.empty(w.m, dtype=torch.float64, device="cuda")
+    sca.sca_residual(P.handle, x, r)
+    sca.sca_step(P.handle, o, 0, 6, x, r)
+    torch.cuda.synchronize()
+    xo, ro, _ = _oracle_rounds(w, prob, 6)
+    assert _rel(x.cpu().numpy(), xo) <= 1e-10 and _rel(r.cpu().numpy(), ro) <= 1e-10
