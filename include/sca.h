@@ -217,7 +217,8 @@ sca_status sca_profile_get(sca_problem* p, double* ms_host, int64_t* launches_ho
  *    grad_cols columns at a time; a second kernel adds the partials to r.  Needs
  *    m <= 20480 (FP32) or m <= 6144 (FP64); grad_cols in {1, 2, 4, 8} is reduced to the
  *    largest group the registers hold for this m; grad_unroll = grad_wg_per_cu = 1.
- *    Rounds with bounded delay (delay_chunks > 1) run the two-pass kernels instead.
+ *    With bounded delay (delay_chunks > 1) each group of a round runs the fused kernel on
+ *    its own coordinates (gradients from the stale residual version).
  *  grad_wg_per_cu in [1, 16]: persistent workgroups per compute unit. */
 typedef struct {
   size_t struct_size; /* = sizeof(sca_launch) */

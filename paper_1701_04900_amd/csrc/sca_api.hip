@@ -497,7 +497,7 @@ static void grad_dense(sca_problem* p, T* x, const T* r, RoundState* st, const i
 #define GRAD_WW_LAUNCH(CC, UU)                                                              \
   hipLaunchKernelGGL((k_grad_br_wwalk<T, CC, UU>), ggrid, dim3(256), 0, s, (const T*)p->A,   \
                      (long long)p->lda, m, r, x, p->d_cn2, list, st, (T*)p->d_dx_sel, bp)
-  if (p->grad_kind == 4) {  // rounds of the fused kind that run the two-pass kernels
+  if (p->grad_kind == 4) {  // (fused problems run k_grad_br_fold; kept as a safe default)
     GRAD_WG_LAUNCH(4, 4);
   } else if (p->grad_kind == 3) {  // one wave per group of columns
     if (p->grad_cols == 4 && p->grad_unroll == 2)
@@ -579,17 +579,19 @@ static bool fused_draws(const sca_problem* p) {
 }
 
 // S.1-S.5 fused (k_grad_br_fold, one workgroup per compute unit, S.1 inside when
-// fs.on), then r += the partials (and the round state advanced when S.1 ran inside).
+// fs.on) on the coordinates listed in 'list' (count and step in *st) with the gradient from
+// r_read, then out = base + the partials (and the round state advanced when S.1 ran inside).
 template <typename T>
-static void grad_fold_dense(sca_problem* p, T* x, T* r, const BRParams& bp, const FusedSel& fs,
-                            hipStream_t s) {
+static void grad_fold_dense(sca_problem* p, T* x, const T* r_read, const T* base, T* out,
+                            RoundState* st, const int* list, const BRParams& bp,
+                            const FusedSel& fs, hipStream_t s) {
   const int m = (int)p->m, G = fused_groups(p);
   const int q = fused_q(p), c = p->grad_cols;
   prof_begin(p, s, SCA_K_GRAD);
 #define FUSED(QQ, CC)                                                                       \
   hipLaunchKernelGGL((k_grad_br_fold<T, QQ, CC>), dim3(G), dim3(1024), 0, s, (const T*)p->A, \
-                     (long long)p->lda, m, (const T*)r, x, p->d_cn2, p->d_sel_cols, p->d_state, \
-                     (T*)p->d_part, (long long)p->ldp, bp, fs)
+                     (long long)p->lda, m, r_read, x, p->d_cn2, list, st, (T*)p->d_part,      \
+                     (long long)p->ldp, bp, fs)
   if constexpr (sizeof(T) == 4) {
     switch (q * 16 + c) {
       case 16 + 8: FUSED(1, 8); break;
@@ -620,7 +622,7 @@ static void grad_fold_dense(sca_problem* p, T* x, T* r, const BRParams& bp, cons
   constexpr int VN = V16<T>::N;
   const int nq = (m + VN - 1) / VN;
   hipLaunchKernelGGL(k_part_reduce<T>, dim3((nq + 63) / 64), dim3(1024), 0, s,
-                     (const T*)p->d_part, (long long)p->ldp, G, m, r, p->d_state, fs.on);
+                     (const T*)p->d_part, (long long)p->ldp, G, m, base, out, st, fs.on);
   prof_end(p, s, 0.0);
 }
 
@@ -630,14 +632,14 @@ static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hi
   FusedSel fs{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
   if (p->grad_kind == 4 && fused_draws(p)) {
     fs.on = 1;
-    grad_fold_dense<T>(p, x, r, bp, fs, s);
+    grad_fold_dense<T>(p, x, r, r, r, p->d_state, p->d_sel_cols, bp, fs, s);
     return;
   }
   prof_begin(p, s, SCA_K_SELECT);
   launch_select(p, o, Tthr, s);
   prof_end(p, s, 0.0);
   if (p->grad_kind == 4) {
-    grad_fold_dense<T>(p, x, r, bp, fs, s);
+    grad_fold_dense<T>(p, x, r, r, r, p->d_state, p->d_sel_cols, bp, fs, s);
     return;
   }
   prof_begin(p, s, SCA_K_GRAD);
@@ -712,9 +714,15 @@ static void launch_round_delayed(sca_problem* p, const sca_opts* o, T* x, T* r, 
   for (int t = 0; t < q; ++t) {
     hipLaunchKernelGGL(k_mb_window, dim3(1), dim3(1024), 0, s, (const RoundState*)p->d_state, t,
                        q, (const int*)p->d_sel_cols, p->d_mbstate, p->d_mbcols);
+    const T* stale_r = slot(std::max<int64_t>(0, t - stale));
+    if (p->grad_kind == 4) {  // the group's S.2-S.5 fused, read from the stale version
+      const FusedSel off{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
+      grad_fold_dense<T>(p, x, stale_r, slot(t), slot(t + 1), p->d_mbstate, p->d_mbcols, bp,
+                         off, s);
+      continue;
+    }
     prof_begin(p, s, SCA_K_GRAD);
-    grad_dense<T>(p, x, slot(std::max<int64_t>(0, t - stale)), p->d_mbstate, p->d_mbcols, bp,
-                  s);
+    grad_dense<T>(p, x, stale_r, p->d_mbstate, p->d_mbcols, bp, s);
     prof_end(p, s, 0.0);
     fold_dense<T>(p, p->d_mbstate, p->d_mbcols, slot(t), slot(t + 1), s);
   }

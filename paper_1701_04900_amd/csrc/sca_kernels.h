@@ -808,13 +808,14 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
   }
 }
 
-// r[i] += sum over w < G of part[w][i]: each lane one 16-byte row group, wave v adds the
-// partials [v*G/16, (v+1)*G/16) in order, then the 16 wave sums are added to r in wave order.
+// r[i] = base[i] + sum over w < G of part[w][i] (base may be r): each lane one 16-byte row
+// group, wave v adds the partials [v*G/16, (v+1)*G/16) in order, then the 16 wave sums are
+// added to base in wave order.
 // With advance != 0 (the block draw ran inside the fused kernel) it also advances the round
 // state the way k_select does: next round, step, drawn-coordinate total.
 template <typename T>
 __global__ void __launch_bounds__(1024)
-k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, T* __restrict__ r,
+k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, const T* base, T* r,
               RoundState* __restrict__ st, int advance) {
   if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
     const double g = st->gamma_next;
@@ -847,13 +848,13 @@ k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, T* __rest
   __syncthreads();
   if (wave == 0 && row < m) {
     if (row + VN <= m) {
-      VA s = *reinterpret_cast<const VA*>(r + row);
+      VA s = *reinterpret_cast<const VA*>(base + row);
 #pragma unroll
       for (int w = 0; w < 16; ++w) s += sh[w][lane];
       *reinterpret_cast<VA*>(r + row) = s;
     } else {
       for (int e = 0; e < m - row; ++e) {
-        T s = r[row + e];
+        T s = base[row + e];
 #pragma unroll
         for (int w = 0; w < 16; ++w) s += sh[w][lane][e];
         r[row + e] = s;

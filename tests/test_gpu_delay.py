@@ -55,6 +55,31 @@ def test_delayed_rounds_match_oracle_fp64(q, s, c_frac, beta):
     P.close()
 
 
+@pytest.mark.parametrize("q,s", [(4, 0), (6, 2), (3, 7)])
+def test_delayed_rounds_fused_kind_fp64(q, s):
+    """The same delayed rounds with every group run by the fused round kernel (launch kind
+    4: the group's gradients from the stale residual version, its moves folded into the
+    next version through the workgroup partials)."""
+    print(f"[gpu] bounded-delay rounds, fused kind, q={q} stale={s}", flush=True)
+    w = inputs.dense_problem(1100, 2500, nnz_frac=0.03, lam_frac=0.03, block=16, p=0.5,
+                             dtype=torch.float64, seed=60 + q)
+    wd = w.to("cuda")
+    P = sca.Problem.from_workload(wd)
+    sca.sca_problem_set_launch(P.handle, 4, 2, 1, 1)
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, delay_chunks=q,
+                      delay_stale=s)
+    gpu = _run_gpu(wd, P, o, 15, 5)
+    prob = O.Problem(A=w.A_numpy(), b=w.b.numpy(), lam=w.lam, block_ptr=w.block_ptr)
+    cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed, delay_chunks=q,
+                      delay_stale=s)
+    x = np.zeros(w.n)
+    r = O.residual(prob, x)
+    for i, k0 in enumerate(range(0, 15, 5)):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k0, 5)
+        assert _rel(gpu[i][0], x) <= 1e-10 and _rel(gpu[i][1], r) <= 1e-10, (q, s, k0)
+    P.close()
+
+
 def test_delayed_rounds_fp32_objective():
     w = inputs.dense_problem(2000, 8000, nnz_frac=0.02, lam_frac=0.02, block=32, p=0.3,
                              dtype=torch.float32, seed=47)
