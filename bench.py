@@ -455,12 +455,12 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
         "counters)",
         "",
         "Commands (repository root, one MI355X; each counter in a run of its own):",
-        "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -- "
-        "python3 bench.py --pmc-probe > gpurun_out/pmc_probe.json",
-        "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -- "
+        "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch -- "
+        "python3 bench.py --pmc-probe > <out>/pmc_probe.json",
+        "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write -- "
         "python3 bench.py --pmc-probe",
-        "  python bench.py --pmc-summarize gpurun_out/pmc_fetch gpurun_out/pmc_write "
-        "gpurun_out/pmc_probe.json",
+        "  python bench.py --pmc-summarize <out>/pmc_fetch <out>/pmc_write "
+        "<out>/pmc_probe.json",
         "",
         "Calibration: k_stream_copy moves exactly 1 GiB each way; the counters read "
         f"{res['FETCH_SIZE']['copy_kib']:.0f} KiB fetched and {res['WRITE_SIZE']['copy_kib']:.0f} KiB "
