@@ -126,7 +126,8 @@ __device__ __forceinline__ Quad<T> load_quad(const T* p) {
 // w takes coordinates 32w..32w+31 of the tile (two 16-row MFMA tiles) against all KP
 // problems (KP/16 MFMA tiles).  Each lane reads four consecutive rows of its coordinate's
 // column (16 bytes) and feeds them to four successive MFMAs, whose K slots are those rows;
-// R's rows are staged in LDS per chunk of kMKC rows.  TA: element type of A; TM: type of R,
+// R's rows are staged in LDS per chunk of kMKC rows, in two alternating buffers (one barrier
+// per chunk).  TA: element type of A; TM: type of R,
 // of the products and of the partials (TM = double with TA = float: FP64 products for
 // probes).
 template <typename TA, typename TM, int NST>
@@ -137,7 +138,8 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
   typedef Mma<TM> M;
   constexpr int KP = NST * 16;
   constexpr int LD = kMKC + 4;  // LDS row stride (keeps every quad 16-byte aligned)
-  __shared__ TM s_r[KP][LD];
+  __shared__ TM s_r[2][KP][LD];
+  int cc = 0;  // chunks staged so far (LDS buffer cc & 1)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int S = *S_ptr;
   const int sp = blockIdx.y;
@@ -202,22 +204,23 @@ k_mgrad(const TA* __restrict__ A, long long lda, int m, const TM* __restrict__ R
           }
         }
       }
-      __syncthreads();
+      const int bb = cc & 1;
 #pragma unroll
       for (int i = 0; i < NQ; ++i) {
         const int q = threadIdx.x + 256 * i;
         if (q < KP * (kMKC / 4)) {
           const int j = q / (kMKC / 4), rr = 4 * (q % (kMKC / 4));
 #pragma unroll
-          for (int u = 0; u < 4; ++u) s_r[j][rr + u] = rq[i].v[u];
+          for (int u = 0; u < 4; ++u) s_r[bb][j][rr + u] = rq[i].v[u];
         }
       }
       __syncthreads();
+      ++cc;
 #pragma unroll
       for (int step = 0; step < kMKC / 16; ++step) {
         Quad<TM> bq[NST];
 #pragma unroll
-        for (int s = 0; s < NST; ++s) bq[s] = load_quad<TM>(&s_r[16 * s + li][16 * step + 4 * kq]);
+        for (int s = 0; s < NST; ++s) bq[s] = load_quad<TM>(&s_r[bb][16 * s + li][16 * step + 4 * kq]);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -332,7 +335,8 @@ __global__ void k_mprobe_final(const double* __restrict__ pmax, const int* __res
 // (i, k) of an MFMA reads the 16-byte quad of rows 4i..4i+3 (of the wave's 64) of entry
 // k's column and feeds component u to MFMA u, whose result rows are 4i + u: four MFMAs per
 // problem tile cover the 64 rows.  Entries are staged kMEC at a time (their rows of D in
-// LDS); the chunk's A quads are issued before the staging.  (Loading the next chunk into
+// LDS, two alternating buffers: one barrier per chunk); the chunk's A quads are issued
+// before the staging.  (Loading the next chunk into
 // registers during the current one measured slower: it halves the waves per SIMD.)
 template <typename TA, typename TD, typename TM, int NST>
 __global__ void __launch_bounds__(256)
@@ -341,7 +345,8 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
         const RoundState* __restrict__ st, TM* __restrict__ P, long long ldp) {
   typedef Mma<TM> M;
   constexpr int KP = NST * 16;
-  __shared__ TM s_d[kMEC][KP + 1];
+  __shared__ TM s_d[2][kMEC][KP + 1];
+  int cc = 0;  // chunks staged so far (LDS buffer cc & 1)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, li = lane & 15;
   const int Jn = st->J_cnt;
@@ -375,19 +380,20 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
         }
       }
     }
-    __syncthreads();
+    const int bb = cc & 1;
     for (int q = threadIdx.x; q < kMEC * KP; q += 256) {
       const int ee = q / KP, j = q % KP;
       const int e = e0 + ee;
-      s_d[ee][j] = e < ehi ? (TM)D[(size_t)J[e] * KP + j] : (TM)0;
+      s_d[bb][ee][j] = e < ehi ? (TM)D[(size_t)J[e] * KP + j] : (TM)0;
     }
     __syncthreads();
+    ++cc;
 #pragma unroll
     for (int step = 0; step < kMEC / 4; ++step) {
       const int ee = 4 * step + kq;
 #pragma unroll
       for (int s = 0; s < NST; ++s) {
-        const TM b = s_d[ee][16 * s + li];
+        const TM b = s_d[bb][ee][16 * s + li];
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[u][s] = M::mma(a[step].v[u], b, acc[u][s]);
       }
