@@ -43,6 +43,8 @@ struct sca_multi {
   int* d_chunk = nullptr;
   int* d_J = nullptr;        // compacted positions (n)
   void* d_Jv = nullptr;      // compaction values (n, unused)
+  int* d_Jc = nullptr;       // column of each listed entry (n)
+  void* d_DJ = nullptr;      // rows of the moves (or X) of the listed entries: n x KP (FP64 room)
   void* d_Rp = nullptr;      // fold partials: kMFS x m x KP (FP64 room)
   void* d_R = nullptr;       // running residual of sca_multi_solve (lda x K, dtype)
   double* d_R64 = nullptr;   // FP64 residual (lda x K)
@@ -329,8 +331,24 @@ __global__ void k_mprobe_final(const double* __restrict__ pmax, const int* __res
   nnz[j] = (int)c2;
 }
 
+// Listed entries gathered for the fold: Jc[e] = colmap ? colmap[J[e]] : J[e] (the column)
+// and DJ[e][j] = D[J[e]][j] (its row of moves), one wave per entry; the fold then reads
+// each with one load instead of a chain of dependent ones.
+template <typename TD>
+__global__ void __launch_bounds__(256)
+k_mgather(const int* __restrict__ J, const int* __restrict__ colmap, const TD* __restrict__ D,
+          int KP, const RoundState* __restrict__ st, int* __restrict__ Jc, TD* __restrict__ DJ) {
+  const int Jn = st->J_cnt;
+  const int lane = threadIdx.x & 63;
+  for (int e = blockIdx.x * 4 + (threadIdx.x >> 6); e < Jn; e += gridDim.x * 4) {
+    const int t = J[e];
+    if (lane == 0) Jc[e] = colmap ? colmap[t] : t;
+    for (int j = lane; j < KP; j += 64) DJ[(size_t)e * KP + j] = D[(size_t)t * KP + j];
+  }
+}
+
 // Fold partials P[sp][r][j] = sum over list entries e of split sp (ascending) of
-// A[r][col(e)] * D[t(e)][j], t(e) = J[e], col(e) = colmap ? colmap[t(e)] : t(e).
+// A[r][Jc[e]] * DJ[e][j] (k_mgather).
 // Workgroup tile: kMFR rows x KP problems; wave w takes rows 64w..64w+63 of the tile.  Lane
 // (i, k) of an MFMA reads the 16-byte quad of rows 4i..4i+3 (of the wave's 64) of entry
 // k's column and feeds component u to MFMA u, whose result rows are 4i + u: four MFMAs per
@@ -340,9 +358,9 @@ __global__ void k_mprobe_final(const double* __restrict__ pmax, const int* __res
 // registers during the current one measured slower: it halves the waves per SIMD.)
 template <typename TA, typename TD, typename TM, int NST>
 __global__ void __launch_bounds__(256)
-k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D,
-        const int* __restrict__ J, const int* __restrict__ colmap,
-        const RoundState* __restrict__ st, TM* __restrict__ P, long long ldp) {
+k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ DJ,
+        const int* __restrict__ Jc, const RoundState* __restrict__ st, TM* __restrict__ P,
+        long long ldp) {
   typedef Mma<TM> M;
   constexpr int KP = NST * 16;
   __shared__ TM s_d[2][kMEC][KP + 1];
@@ -367,8 +385,7 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
 #pragma unroll
       for (int u = 0; u < 4; ++u) a[step].v[u] = (TM)0;
       if (e < ehi && rb < m) {
-        const int col = colmap ? colmap[J[e]] : J[e];
-        const TA* p = A + (size_t)col * lda + rb;
+        const TA* p = A + (size_t)Jc[e] * lda + rb;
         if (rb + 3 < m) {
           const Quad<TA> qa = load_quad<TA>(p);
 #pragma unroll
@@ -384,7 +401,7 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
     for (int q = threadIdx.x; q < kMEC * KP; q += 256) {
       const int ee = q / KP, j = q % KP;
       const int e = e0 + ee;
-      s_d[bb][ee][j] = e < ehi ? (TM)D[(size_t)J[e] * KP + j] : (TM)0;
+      s_d[bb][ee][j] = e < ehi ? (TM)DJ[(size_t)e * KP + j] : (TM)0;
     }
     __syncthreads();
     ++cc;
@@ -627,26 +644,27 @@ void launch_mfold(sca_multi* M, const TD* D, const int* colmap, TM* P, hipStream
   const dim3 grid((unsigned)((M->m + kMFR - 1) / kMFR), kMFS);
   const TA* A = (const TA*)M->A;
   const int m = (int)M->m;
+  const int ggrid = (int)std::max<int64_t>(1, std::min<int64_t>((M->n + 3) / 4, 8 * M->ncu));
+  hipLaunchKernelGGL(k_mgather<TD>, dim3(ggrid), dim3(256), 0, s, (const int*)M->d_J, colmap, D,
+                     (int)M->KP, (const RoundState*)M->d_state, M->d_Jc, (TD*)M->d_DJ);
+  const TD* DJ = (const TD*)M->d_DJ;
+  const int* Jc = (const int*)M->d_Jc;
   switch (M->KP / 16) {
     case 1:
       hipLaunchKernelGGL((k_mfold<TA, TD, TM, 1>), grid, dim3(256), 0, s, A, (long long)M->lda,
-                         m, D, (const int*)M->d_J, colmap, (const RoundState*)M->d_state, P,
-                         ldp_of(M));
+                         m, DJ, Jc, (const RoundState*)M->d_state, P, ldp_of(M));
       break;
     case 2:
       hipLaunchKernelGGL((k_mfold<TA, TD, TM, 2>), grid, dim3(256), 0, s, A, (long long)M->lda,
-                         m, D, (const int*)M->d_J, colmap, (const RoundState*)M->d_state, P,
-                         ldp_of(M));
+                         m, DJ, Jc, (const RoundState*)M->d_state, P, ldp_of(M));
       break;
     case 3:
       hipLaunchKernelGGL((k_mfold<TA, TD, TM, 3>), grid, dim3(256), 0, s, A, (long long)M->lda,
-                         m, D, (const int*)M->d_J, colmap, (const RoundState*)M->d_state, P,
-                         ldp_of(M));
+                         m, DJ, Jc, (const RoundState*)M->d_state, P, ldp_of(M));
       break;
     default:
       hipLaunchKernelGGL((k_mfold<TA, TD, TM, 4>), grid, dim3(256), 0, s, A, (long long)M->lda,
-                         m, D, (const int*)M->d_J, colmap, (const RoundState*)M->d_state, P,
-                         ldp_of(M));
+                         m, DJ, Jc, (const RoundState*)M->d_state, P, ldp_of(M));
       break;
   }
 }
@@ -780,7 +798,7 @@ void mfree(sca_multi* M) {
                   M->d_iota, M->d_nall,  M->d_G,    M->d_D,     M->d_mv,    M->d_chunk,
                   M->d_J,   M->d_Jv,     M->d_Rp,   M->d_R,     M->d_R64,   M->d_Xt,
                   M->d_active, M->d_done, M->d_F,   M->d_mer,   M->d_nnz,   M->d_part,
-                  M->d_upd};
+                  M->d_upd, M->d_Jc, M->d_DJ};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (M->graph) (void)hipGraphExecDestroy(M->graph);
@@ -859,6 +877,8 @@ extern "C" sca_status sca_multi_create(sca_multi** out, sca_dtype dtype, int64_t
   MALLOC(M->d_chunk, sizeof(int) * ((n + kChunk - 1) / kChunk + 1));
   MALLOC(M->d_J, sizeof(int) * n);
   MALLOC(M->d_Jv, es * n);
+  MALLOC(M->d_Jc, sizeof(int) * n);
+  MALLOC(M->d_DJ, sizeof(double) * (size_t)n * KP);
   MALLOC(M->d_Rp, sizeof(double) * kMFS * (size_t)m * KP);
   MALLOC(M->d_R, es * (size_t)lda * K);
   MALLOC(M->d_R64, sizeof(double) * (size_t)lda * K);
