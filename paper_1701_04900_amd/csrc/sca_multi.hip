@@ -76,7 +76,7 @@ constexpr int kMTC = 128;  // gradient tile: drawn coordinates per workgroup
 constexpr int kMKC = 32;   // gradient: rows of R staged per LDS chunk
 constexpr int kMNS = 16;   // gradient: row splits (partials reduced in the best response)
 constexpr int kMFR = 256;  // fold tile: rows per workgroup (64 per wave)
-constexpr int kMEC = 32;   // fold: list entries staged per LDS chunk
+constexpr int kMEC = 16;   // fold: list entries staged per LDS chunk
 constexpr int kMFS = 32;   // fold: list splits (partials reduced in the fold reduction)
 constexpr int kMaxK = 64;
 
@@ -353,9 +353,9 @@ k_mgather(const int* __restrict__ J, const int* __restrict__ colmap, const TD* _
 // (i, k) of an MFMA reads the 16-byte quad of rows 4i..4i+3 (of the wave's 64) of entry
 // k's column and feeds component u to MFMA u, whose result rows are 4i + u: four MFMAs per
 // problem tile cover the 64 rows.  Entries are staged kMEC at a time (their rows of D in
-// LDS, two alternating buffers: one barrier per chunk); the chunk's A quads are issued
-// before the staging.  (Loading the next chunk into
-// registers during the current one measured slower: it halves the waves per SIMD.)
+// LDS, two alternating buffers: one barrier per chunk); the next chunk's A quads are loaded
+// into registers while the current chunk computes (16-entry chunks keep the registers of
+// the two chunks at those of one 32-entry chunk).
 template <typename TA, typename TD, typename TM, int NST>
 __global__ void __launch_bounds__(256)
 k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ DJ,
@@ -377,26 +377,43 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int s = 0; s < NST; ++s) acc[u][s] = (typename M::acc){0, 0, 0, 0};
-  for (int e0 = elo; e0 < ehi; e0 += kMEC) {
-    Quad<TM> a[kMEC / 4];
+  // A quads of chunk e0 into dst.  FP32: every lane loads (entries past the split repeat
+  // the split's last entry, whose staged moves are zero; rows past m read rows m..lda-1 or
+  // are clamped to the last row quad, and their results are never stored), so the loads
+  // carry no branches and the next chunk's loads stay in flight while this one computes.
+  const int mq4 = (m + 3) / 4 * 4;
+  auto load_chunk = [&](int e0, Quad<TM> (&dst)[kMEC / 4]) {
 #pragma unroll
     for (int step = 0; step < kMEC / 4; ++step) {
       const int e = e0 + 4 * step + kq;
+      if constexpr (sizeof(TA) == 4) {
+        const TA* p = A + (size_t)Jc[min(e, ehi - 1)] * lda + min(rb, mq4 - 4);
+        const Quad<TA> qa = load_quad<TA>(p);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[step].v[u] = (TM)0;
-      if (e < ehi && rb < m) {
-        const TA* p = A + (size_t)Jc[e] * lda + rb;
-        if (rb + 3 < m) {
-          const Quad<TA> qa = load_quad<TA>(p);
+        for (int u = 0; u < 4; ++u) dst[step].v[u] = (TM)qa.v[u];
+      } else {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a[step].v[u] = (TM)qa.v[u];
-        } else {
+        for (int u = 0; u < 4; ++u) dst[step].v[u] = (TM)0;
+        if (e < ehi && rb < m) {
+          const TA* p = A + (size_t)Jc[e] * lda + rb;
+          if (rb + 3 < m) {
+            const Quad<TA> qa = load_quad<TA>(p);
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (rb + u < m) a[step].v[u] = (TM)p[u];
+            for (int u = 0; u < 4; ++u) dst[step].v[u] = (TM)qa.v[u];
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (rb + u < m) dst[step].v[u] = (TM)p[u];
+          }
         }
       }
     }
+  };
+  Quad<TM> a[kMEC / 4];
+  if (elo < ehi) load_chunk(elo, a);
+  for (int e0 = elo; e0 < ehi; e0 += kMEC) {
+    Quad<TM> an[kMEC / 4];
+    load_chunk(e0 + kMEC, an);
     const int bb = cc & 1;
     for (int q = threadIdx.x; q < kMEC * KP; q += 256) {
       const int ee = q / KP, j = q % KP;
@@ -415,6 +432,8 @@ k_mfold(const TA* __restrict__ A, long long lda, int m, const TD* __restrict__ D
         for (int u = 0; u < 4; ++u) acc[u][s] = M::mma(a[step].v[u], b, acc[u][s]);
       }
     }
+#pragma unroll
+    for (int step = 0; step < kMEC / 4; ++step) a[step] = an[step];
   }
   const int wr = blockIdx.x * kMFR + 64 * wave;
 #pragma unroll
