@@ -779,7 +779,7 @@ def bench_single(args):
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        cr = args.cpu_rounds or {"lasso": 12, "nonconvex": 100, "sparse": 100}[kind]
+        cr = args.cpu_rounds or {"lasso": 16, "nonconvex": 100, "sparse": 100}[kind]
         cpu = cpu_baseline(w, opts_kw, cr)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f} s: {cpu}")
 
