@@ -168,3 +168,23 @@ def test_long_drawn_list_sparse():
     torch.cuda.synchronize()
     xo, ro, _ = _oracle_rounds(w, prob, 6)
     assert _rel(x.cpu().numpy(), xo) <= 1e-10 and _rel(r.cpu().numpy(), ro) <= 1e-10
+
+
+@pytest.mark.parametrize("kind,dtype", [("fused", torch.float64), ("fused", torch.float32),
+                                        ("two_pass", torch.float64)])
+def test_padding_rows_of_A_never_reach_a_result(kind, dtype):
+    """A's rows m..lda-1 filled with NaN (lda = 1004 for m = 1001): the kernels that load
+    whole 16-byte row groups must zero or discard them."""
+    w = inputs.dense_problem(1001, 3000, nnz_frac=0.02, lam_frac=0.02, block=32, p=0.5,
+                             dtype=dtype, seed=48)
+    assert w.lda > w.m
+    prob = _oracle(w)
+    w.At[:, w.m:] = float("nan")
+    run = Run(w, kind)
+    xg, rg = run.step(10)
+    assert np.all(np.isfinite(xg)) and np.all(np.isfinite(rg))
+    xo, ro, _ = _oracle_rounds(w, prob, 10)
+    tol = 1e-10 if dtype == torch.float64 else 1e-3
+    assert _rel(xg, xo) <= tol and _rel(rg, ro) <= tol
+    rep = sca.sca_objective(run.P.handle, run.opts, run.x)
+    assert math.isfinite(rep["F"]) and math.isfinite(rep["merit"])

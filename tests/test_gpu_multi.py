@@ -188,3 +188,26 @@ def test_multi_rejects_bad_arguments():
         sca.sca_multi_solve(M.handle, _opts(w, max_rounds=10, tol_rel_obj=1e-6), X, w.K)
     assert e.value.status == sca.SCA_EINVAL
     M.close()
+
+
+def test_multi_fp32_ragged_rows_with_nan_padding():
+    """m = 1001 (lda 1004) with A's padding rows set to NaN: the fold's whole-row-group loads
+    must discard them; objectives against the oracle per problem."""
+    w = inputs.multi_rhs_problem(1001, 3000, 9, rhs="perturbed", block=32, p=0.4,
+                                 dtype=torch.float32, seed=17)
+    assert w.lda > w.m
+    probs = {k: _oracle(w, k) for k in (0, 4, 8)}
+    w.At[:, w.m:] = float("nan")
+    M, X, R = _setup(w)
+    o = _opts(w)
+    sca.sca_multi_step(M.handle, o, 0, 20, X, R)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(X).all()) and bool(torch.isfinite(R[:, : w.m]).all())
+    rep = sca.sca_multi_objective(M.handle, o, X, w.K)
+    for k, prob in probs.items():
+        x, r, _ = O.run_rounds(prob, _cfg(w), np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0,
+                               20)
+        Fo = O.objective(prob, x, r)
+        assert abs(rep["F"][k] - Fo) <= 1e-4 * abs(Fo), k
+        assert _rel(X[k].double().cpu().numpy(), x) <= 1e-3, k
+    M.close()
