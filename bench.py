@@ -632,6 +632,10 @@ def round_alg_bytes(L, drawn, m, esize, groups):
 
 def grad_kernel_name(L, sparse, m=0):
     if sparse:
+        # panel split (r in at most 16 panels of 140 KiB): partial dot products, then the sum
+        # of the partials with the best response (one timed step, two kernels)
+        if (m + 35839) // 35840 <= 16:
+            return "k_dot_split<float,8> + k_br_split<float,8>"
         return "k_grad_br_cscp<float,8>"
     if L["grad_kind"] == 4:
         return f"k_grad_br_fold<float,{fused_q(m, 4)},{L['grad_cols']}>"
@@ -754,7 +758,8 @@ def bench_single(args):
             fold_b = float(f["launches"]) * (G + 2) * w.m * esize
         cands = [("grad", g, grad_b, grad_kernel_name(L, sparse, w.m))]
         if sparse:
-            cands.append(("fold", f, fold_b, "k_fold_csc<float> + k_fold_csc_finish<float>"))
+            cands.append(("fold", f, fold_b,
+                          "k_bin_scan<4> + k_bin_scatter<float,8> + k_bin_acc<float,float,float>"))
         step, kp, kb, kname = max(cands, key=lambda c: c[1]["ms"])
         achieved = kb / (kp["ms"] * 1e-3) / 1e9
         traffic = pmc_traffic(L) if kind == "lasso" and step == "grad" else None

@@ -272,7 +272,7 @@ void sca::free_workspace(sca_problem* p) {
                   p->d_J_idx, p->d_J_val, p->d_part, p->d_r64, p->d_rtmp, p->d_scal,
                   p->d_int, p->d_obj_part, p->d_wmax, p->d_wsum, p->d_wcnt,
                   p->csc_colptr, p->csc_rowidx, p->csc_vals, p->d_bin_cnt, p->d_bin_tot,
-                  p->d_bin_moved, p->d_ent};
+                  p->d_bin_moved, p->d_ent, p->d_pofs, p->d_sp_part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   adjoint_release(p->adj);

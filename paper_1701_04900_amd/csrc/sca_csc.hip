@@ -172,14 +172,14 @@ __device__ __forceinline__ void flush_counts(const int* hist, int nb, int moved,
 
 // Best response and step of drawn coordinate t (column j) from its dot product a_j^T r;
 // every lane of the group computes the same d, lane 0 stores.
+// The same from x_j and ||a_j||^2 already loaded.
 template <typename T>
-__device__ __forceinline__ T csc_step(T dot, int j, int t, int sub, T gamma, T* __restrict__ x,
-                                      const double* __restrict__ cn2, T* __restrict__ dx_sel,
-                                      const BRParams& bp) {
-  const T xj = x[j];
+__device__ __forceinline__ T csc_step_v(T dot, T xj, double cn2j, int j, int t, int sub, T gamma,
+                                        T* __restrict__ x, T* __restrict__ dx_sel,
+                                        const BRParams& bp) {
   T g = dot - (T)bp.c2 * xj;
   if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
-  const T q = (T)(cn2[j] + bp.tau);
+  const T q = (T)(cn2j + bp.tau);
   const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
   const T d = gamma * (xh - xj);
   if (sub == 0) {
@@ -187,6 +187,13 @@ __device__ __forceinline__ T csc_step(T dot, int j, int t, int sub, T gamma, T* 
     dx_sel[t] = d;
   }
   return d;
+}
+
+template <typename T>
+__device__ __forceinline__ T csc_step(T dot, int j, int t, int sub, T gamma, T* __restrict__ x,
+                                      const double* __restrict__ cn2, T* __restrict__ dx_sel,
+                                      const BRParams& bp) {
+  return csc_step_v<T>(dot, x[j], cn2[j], j, t, sub, gamma, x, dx_sel, bp);
 }
 
 // S.2 + S.4 on sparse columns with r gathered from memory (used when the panel kernel
@@ -319,41 +326,306 @@ k_grad_br_cscp(const long long* __restrict__ colptr, const int* __restrict__ row
         }
       }
       __syncthreads();
+      // windows that lay wholly inside the panel continue with the next 32 entries; the
+      // loads of all such columns are issued together
+      bool more = true;
+      while (more) {
+        more = false;
 #pragma unroll
-      for (int i = 0; i < CPG; ++i) {
-        int nin = 0;
+        for (int i = 0; i < CPG; ++i) {
+          int nin = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const bool in = rw[i][h] < hi;
-          if (in) acc[i] += vw[i][h] * s_r[rw[i][h] - lo];
-          nin += __popcll((__ballot(in) >> gshift) & 0xffffull);
-        }
-        kc[i] += nin;
-        while (nin == 32) {  // the whole window was inside the panel: next window
-          nin = 0;
           for (int h = 0; h < 2; ++h) {
-            const int k = kc[i] + sub + 16 * h;
-            const int rr = k < ke[i] ? rowidx[k] : INT_MAX;
-            const bool in = rr < hi;
-            if (in) acc[i] += v[k] * s_r[rr - lo];
+            const bool in = rw[i][h] < hi;
+            if (in) acc[i] += vw[i][h] * s_r[rw[i][h] - lo];
             nin += __popcll((__ballot(in) >> gshift) & 0xffffull);
           }
           kc[i] += nin;
+          const bool full = nin == 32;
+          more |= full;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int k = kc[i] + sub + 16 * h;
+            rw[i][h] = full && k < ke[i] ? rowidx[k] : INT_MAX;
+            vw[i][h] = full && k < ke[i] ? v[k] : (T)0;
+          }
         }
       }
+    }
+    // best responses: x_j and ||a_j||^2 of every column of the pass loaded together
+    T xj[CPG];
+    double qj[CPG];
+    int kb[CPG];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      xj[i] = jj[i] >= 0 ? x[jj[i]] : (T)0;
+      qj[i] = jj[i] >= 0 ? cn2[jj[i]] : 0.0;
+      kb[i] = jj[i] >= 0 ? (int)colptr[jj[i]] : 0;
     }
 #pragma unroll
     for (int i = 0; i < CPG; ++i) {
       if (jj[i] < 0) continue;
       const int t = pb + grp + kPanelGroups * i;
-      const T d = csc_step<T>(sum16(acc[i]), jj[i], t, sub, gamma, x, cn2, dx_sel, bp);
-      if (d != (T)0) {
+      const T d = csc_step_v<T>(sum16(acc[i]), xj[i], qj[i], jj[i], t, sub, gamma, x, dx_sel, bp);
+      if (d != (T)0)
         moved += sub == 0;
-        for (long long k = colptr[jj[i]] + sub; k < ke[i]; k += 16)
-          atomicAdd(&hist[rowidx[k] >> bin_log], 1);
+      else
+        kb[i] = ke[i];  // not moved: no bin counts
+    }
+    // bin counts of the moved columns' nonzeros, 64 entries of every moved column per step
+    // (four loads per lane for each column in flight together)
+    for (int o = 0;; o += 64) {
+      int rr[CPG][4];
+#pragma unroll
+      for (int i = 0; i < CPG; ++i)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = kb[i] + o + sub + 16 * u;
+          rr[i][u] = rowidx[jj[i] >= 0 && k < ke[i] ? k : 0];
+        }
+      bool left = false;
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (jj[i] >= 0 && kb[i] + o + sub + 16 * u < ke[i])
+            atomicAdd(&hist[rr[i][u] >> bin_log], 1);
+        left |= jj[i] >= 0 && kb[i] + o + 64 < ke[i];
       }
+      if (!left) break;
     }
     __syncthreads();  // the next pass refills the panels
+  }
+  __syncthreads();
+  flush_counts(hist, nb, moved, s_moved, cnt, moved_wg);
+}
+
+// Panel-split gradient.  The rows are cut into NP <= kSplitMaxPanels panels of PE rows
+// (PE <= kSplitPanelBytes / sizeof(T)); pofs[j * (NP + 1) + P] is the first entry of column
+// j whose row lies in panel P (rows ascend inside a column), written once at create time.
+constexpr int kSplitPanelBytes = 143360;  // 140 KiB of r per workgroup
+constexpr int kSplitMaxPanels = 16;       // one partial per lane of a 16-lane group
+constexpr int kSplitStage = 12;           // r loads per thread in flight while staging
+
+// pofs of every column: a binary search per inner panel boundary.
+__global__ void __launch_bounds__(256)
+k_panel_offsets(const long long* __restrict__ colptr, const int* __restrict__ rowidx, int n,
+                int NP, int PE, int* __restrict__ pofs) {
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+    const int b = (int)colptr[j], e = (int)colptr[j + 1];
+    int* o = pofs + (size_t)j * (NP + 1);
+    o[0] = b;
+    o[NP] = e;
+    for (int P = 1; P < NP; ++P) {
+      const int target = P * PE;
+      int lo = b, hi = e;
+      while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (rowidx[mid] < target)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      o[P] = lo;
+    }
+  }
+}
+
+// Partial dot products a_j^T r over one panel (S.2 of Algorithm 1, first half).  Workgroup
+// w takes panel P = w % NP, stages r's rows of that panel in LDS once, and walks chunk
+// w / NP (of CPP equal chunks) of the drawn list: 16 lanes per drawn coordinate, CPG
+// coordinates per group in flight, the panel's first 48 entries of each loaded at once
+// (longer runs continue four loads at a time); the next pass's panel offsets and the list
+// entries of the pass after it are loaded while the current one computes.  Every load is unconditional (an index past the
+// run reads entry 0, whose value is not used), so no load waits for another's result
+// except through a real dependence.  Lane sub adds the entries sub, sub + 16, ... in order;
+// part[P * ldpart + t] = the 16 lane sums added by sum16.
+template <typename T, int CPG>
+__global__ void __launch_bounds__(1024)
+k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
+            const T* __restrict__ v, const T* __restrict__ r, const int* __restrict__ sel_cols,
+            const RoundState* __restrict__ st, int m, int NP, int PE, int CPP,
+            T* __restrict__ part, long long ldpart) {
+  constexpr int PR = kSplitPanelBytes / (int)sizeof(T);
+  constexpr int G = 1024 / 16;  // groups of 16 lanes
+  constexpr int H = 3;          // 16-entry windows loaded at once per coordinate
+  __shared__ T s_r[PR];
+  const int P = (int)blockIdx.x % NP, c = (int)blockIdx.x / NP;
+  const int lo = P * PE, hi = min(m, lo + PE), len = max(0, hi - lo);
+  const int S = st->S_cnt;
+  const int per = (S + CPP - 1) / CPP;
+  const int c0 = min(S, c * per), c1 = min(S, c0 + per);
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int NP1 = NP + 1;
+  // drawn columns of the coordinates tb + grp + G * i, then their panel offsets [a, b)
+  // (an empty run past c1); the list is read two passes ahead, the offsets one
+  auto load_cols = [&](int tb, int (&jr)[CPG]) {
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int t = tb + grp + G * i;
+      jr[i] = sel_cols[t < c1 ? t : 0];
+    }
+  };
+  auto load_offs = [&](int tb, const int (&jr)[CPG], int (&a)[CPG], int (&b)[CPG]) {
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int t = tb + grp + G * i;
+      const size_t o = (size_t)(t < c1 ? jr[i] : 0) * NP1 + P;
+      a[i] = pofs[o];
+      b[i] = pofs[o + (t < c1 ? 1 : 0)];
+    }
+  };
+  int jn[CPG], ks[CPG], ke[CPG];
+  if (c0 < c1) {  // in flight while r's panel is staged
+    load_cols(c0, jn);
+    load_offs(c0, jn, ks, ke);
+    load_cols(c0 + G * CPG, jn);
+  }
+  for (int base = 0; base < len; base += 1024 * kSplitStage) {
+    T tmp[kSplitStage];
+#pragma unroll
+    for (int u = 0; u < kSplitStage; ++u) {
+      const int i = base + (int)threadIdx.x + u * 1024;
+      tmp[u] = r[lo + (i < len ? i : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < kSplitStage; ++u) {
+      const int i = base + (int)threadIdx.x + u * 1024;
+      if (i < len) s_r[i] = tmp[u];
+    }
+  }
+  __syncthreads();
+  for (int tb = c0; tb < c1; tb += G * CPG) {
+    int rw[CPG][H];
+    T vw[CPG][H];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i)
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int k = ks[i] + sub + 16 * h;
+        const int kk = k < ke[i] ? k : 0;
+        rw[i][h] = rowidx[kk];
+        vw[i][h] = v[kk];
+      }
+    int ks2[CPG], ke2[CPG];
+    load_offs(tb + G * CPG, jn, ks2, ke2);
+    load_cols(tb + 2 * G * CPG, jn);
+    // r at the window rows (row lo for lanes past the run: read, not used)
+    T rv[CPG][H];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i)
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        rv[i][h] = s_r[ks[i] + sub + 16 * h < ke[i] ? rw[i][h] - lo : 0];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      T acc = (T)0;
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const T a2 = acc + vw[i][h] * rv[i][h];
+        acc = ks[i] + sub + 16 * h < ke[i] ? a2 : acc;
+      }
+      for (int k0 = ks[i] + sub + 16 * H; k0 < ke[i]; k0 += 64) {
+        int rq[4];
+        T vq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 16 * u;
+          const int kk = k < ke[i] ? k : 0;
+          rq[u] = rowidx[kk];
+          vq[u] = v[kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + 16 * u < ke[i]) acc += vq[u] * s_r[rq[u] - lo];
+      }
+      acc = sum16(acc);
+      const int t = tb + grp + G * i;
+      if (sub == 0 && t < c1) part[(size_t)P * ldpart + t] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      ks[i] = ks2[i];
+      ke[i] = ke2[i];
+    }
+  }
+}
+
+// S.2 (second half) + S.4 after k_dot_split: the NP partials of each drawn coordinate are
+// added by sum16 (lane sub holds panel sub's), then the best response and the step; the
+// moved columns' nonzeros are counted per row bin (64 entries of every moved column per
+// step).  Loads are unconditional as in k_dot_split.  Same work mapping and outputs as
+// k_grad_br_csc.
+template <typename T, int CPG>
+__global__ void __launch_bounds__(kCscThreads)
+k_br_split(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
+           const T* __restrict__ part, long long ldpart, int NP, T* __restrict__ x,
+           const double* __restrict__ cn2, const int* __restrict__ sel_cols,
+           const RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp, int bin_log,
+           int nb, int* __restrict__ cnt, int* __restrict__ moved_wg) {
+  extern __shared__ int hist[];
+  __shared__ int s_moved[kCscThreads / 64];
+  for (int i = threadIdx.x; i < nb; i += kCscThreads) hist[i] = 0;
+  __syncthreads();
+  constexpr int G = kCscThreads / 16;
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const T gamma = (T)st->gamma_cur;
+  int c0, c1;
+  wg_chunk(st->S_cnt, &c0, &c1);
+  int moved = 0;
+  for (int tb = c0; tb < c1; tb += G * CPG) {
+    int jj[CPG], kb[CPG], ke[CPG];
+    T pv[CPG], xj[CPG];
+    double qj[CPG];
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int t = tb + grp + G * i;
+      const bool ok = t < c1;
+      jj[i] = sel_cols[ok ? t : 0];
+      pv[i] = part[ok && sub < NP ? (size_t)sub * ldpart + t : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int t = tb + grp + G * i;
+      const int j = t < c1 ? jj[i] : 0;
+      xj[i] = x[j];
+      qj[i] = cn2[j];
+      kb[i] = (int)colptr[j];
+      ke[i] = (int)colptr[j + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < CPG; ++i) {
+      const int t = tb + grp + G * i;
+      const T dot = sum16(t < c1 && sub < NP ? pv[i] : (T)0);
+      if (t >= c1) {
+        ke[i] = kb[i];  // no coordinate: no bin counts
+        continue;
+      }
+      const T d = csc_step_v<T>(dot, xj[i], qj[i], jj[i], t, sub, gamma, x, dx_sel, bp);
+      if (d != (T)0)
+        moved += sub == 0;
+      else
+        ke[i] = kb[i];  // not moved: no bin counts
+    }
+    for (int o = 0;; o += 64) {
+      int rr[CPG][4];
+#pragma unroll
+      for (int i = 0; i < CPG; ++i)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = kb[i] + o + sub + 16 * u;
+          rr[i][u] = rowidx[k < ke[i] ? k : 0];
+        }
+      bool left = false;
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (kb[i] + o + sub + 16 * u < ke[i]) atomicAdd(&hist[rr[i][u] >> bin_log], 1);
+        left |= kb[i] + o + 64 < ke[i];
+      }
+      if (!left) break;
+    }
   }
   __syncthreads();
   flush_counts(hist, nb, moved, s_moved, cnt, moved_wg);
@@ -690,7 +962,20 @@ void grad_launch(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream
 
 template <typename T>
 void grad_any(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream_t s) {
-  if (p->bin_panel) {
+  if (p->sp_np > 0) {
+    constexpr int CPG = sizeof(T) == 4 ? 8 : 4;
+    const int NP = p->sp_np, CPP = std::max(1, p->ncu / NP);
+    const long long ldpart = std::max<long long>(1, p->n);
+    hipLaunchKernelGGL((k_dot_split<T, CPG>), dim3(NP * CPP), dim3(1024), 0, s,
+                       (const int*)p->d_pofs, (const int*)p->csc_rowidx, (const T*)p->csc_vals,
+                       r, p->d_sel_cols, (const RoundState*)p->d_state, (int)p->m, NP, p->sp_pe,
+                       CPP, (T*)p->d_sp_part, ldpart);
+    hipLaunchKernelGGL((k_br_split<T, CPG>), dim3(p->bin_grid), dim3(kCscThreads),
+                       sizeof(int) * p->bin_nb, s, (const long long*)p->csc_colptr,
+                       (const int*)p->csc_rowidx, (const T*)p->d_sp_part, ldpart, NP, x,
+                       p->d_cn2, p->d_sel_cols, (const RoundState*)p->d_state, (T*)p->d_dx_sel,
+                       bp, p->bin_log, p->bin_nb, p->d_bin_cnt, p->d_bin_moved);
+  } else if (p->bin_panel) {
     hipLaunchKernelGGL((k_grad_br_cscp<T, sizeof(T) == 4 ? 8 : 4>), dim3(p->bin_grid),
                        dim3(kPanelThreads), 0, s,
                        (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
@@ -864,6 +1149,30 @@ static sca_status build_csc(sca_problem* p, const long long* rowptr, const int32
   return SCA_OK;
 }
 
+// Panel-split gradient set-up: panels of at most kSplitPanelBytes of r; problems that need
+// more than kSplitMaxPanels keep the panel-walk (or gather) gradient.
+static sca_status split_setup(sca_problem* p, hipStream_t s) {
+  const int64_t PR = kSplitPanelBytes / (int64_t)p->esize;
+  const int64_t NP = (p->m + PR - 1) / PR;
+  if (NP < 1 || NP > kSplitMaxPanels) return SCA_OK;
+  const int64_t PE = ((p->m + NP - 1) / NP + 63) / 64 * 64;
+  const size_t n1 = (size_t)std::max<int64_t>(1, p->n);
+  sca_status st;
+  if ((st = dev_alloc((void**)&p->d_pofs, sizeof(int) * n1 * (size_t)(NP + 1))) != SCA_OK ||
+      (st = dev_alloc(&p->d_sp_part, p->esize * n1 * (size_t)NP)) != SCA_OK)
+    return st;
+  if (p->n > 0) {
+    const int grid = (int)std::min<int64_t>((p->n + 255) / 256, 8 * (int64_t)p->ncu);
+    hipLaunchKernelGGL(k_panel_offsets, dim3(grid), dim3(256), 0, s,
+                       (const long long*)p->csc_colptr, (const int*)p->csc_rowidx, (int)p->n,
+                       (int)NP, (int)PE, p->d_pofs);
+    if (hipGetLastError() != hipSuccess) return set_error(SCA_EHIP, "panel offsets failed");
+  }
+  p->sp_np = (int)NP;
+  p->sp_pe = (int)PE;
+  return SCA_OK;
+}
+
 extern "C" sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype, int64_t m,
                                              int64_t n, int64_t nnz, const int64_t* rowptr,
                                              const int32_t* colidx, const void* vals,
@@ -912,6 +1221,7 @@ extern "C" sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype,
              ? build_csc<float>(p, (const long long*)rowptr, colidx, (const float*)vals, s)
              : build_csc<double>(p, (const long long*)rowptr, colidx, (const double*)vals, s);
   }
+  if (st == SCA_OK) st = split_setup(p, s);
   if (st == SCA_OK) st = finish_create(p, s);
   if (st != SCA_OK) {
     free_workspace(p);

@@ -39,6 +39,12 @@ struct sca_problem {
   // grid, bin totals, moved columns per workgroup, and up to nnz (row, value) entries
   int bin_log = 0, bin_nb = 0, bin_grid = 0, bin_unroll = 8;
   bool bin_panel = true;  // gradient with r staged in LDS panels
+  // panel-split gradient (sp_np > 0): rows in sp_np panels of sp_pe rows; pofs[j][P] is the
+  // first entry of column j in panel P (n x (sp_np + 1) ints); sp_part holds one partial
+  // dot product per (panel, drawn coordinate) (sp_np x n, dtype)
+  int sp_np = 0, sp_pe = 0;
+  int* d_pofs = nullptr;
+  void* d_sp_part = nullptr;
   int* d_bin_cnt = nullptr;
   int* d_bin_tot = nullptr;
   int* d_bin_moved = nullptr;
