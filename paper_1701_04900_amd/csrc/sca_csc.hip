@@ -726,8 +726,9 @@ __device__ __forceinline__ void put_ent(Ent<double>* e, long long pos, uint32_t 
 
 // Writes the entries (row within bin, a_ij * coef) of the listed columns with coef != 0
 // into their bins' slots.  list == nullptr: the columns 0..count-1 with coef indexed by j;
-// otherwise list[t] with coef indexed by t.  Same work mapping as the counting kernel; a
-// column's nonzeros are loaded 16*U at a time before their slots are taken.
+// otherwise list[t] with coef indexed by t.  Same work mapping as the counting kernel; each
+// group of 16 lanes takes 16/U columns at once and loads 16*U nonzeros of each per step,
+// all before their slots are taken.
 template <typename T, int U>
 __global__ void __launch_bounds__(kCscThreads)
 k_bin_scatter(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
@@ -741,31 +742,56 @@ k_bin_scatter(const long long* __restrict__ colptr, const int* __restrict__ rowi
   __syncthreads();
   for (int i = threadIdx.x; i < nb; i += kCscThreads) cursor[i] += off[(size_t)blockIdx.x * nb + i];
   __syncthreads();
-  const int sub = threadIdx.x & 15;
+  constexpr int G = kCscThreads / 16;
+  constexpr int CPG = 16 / U;  // columns per group in flight
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const uint32_t rmask = (1u << bin_log) - 1u;
   int c0, c1;
   wg_chunk(count_ptr ? *count_ptr : count, &c0, &c1);
-  for (int t = c0 + (int)(threadIdx.x >> 4); t < c1; t += kCscThreads / 16) {
-    const int j = list ? list[t] : t;
-    const T d = coef[t];
-    if (d == (T)0) continue;
-    const long long b = colptr[j], e = colptr[j + 1];
-    for (long long k0 = b; k0 < e; k0 += 16 * U) {
-      int ri[U];
-      T vv[U];
+  // the columns t = tb + grp + G * i (the same ones, per workgroup, as the counting
+  // kernels); loads are unconditional (clamped to valid positions, their values unused)
+  for (int tb = c0; tb < c1; tb += G * CPG) {
+    int jr[CPG], kb[CPG], ke[CPG];
+    T d[CPG];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const long long k = k0 + sub + 16 * u;
-        ri[u] = k < e ? rowidx[k] : -1;
-        vv[u] = k < e ? v[k] : (T)0;
-      }
+    for (int i = 0; i < CPG; ++i) {
+      const int t = tb + grp + G * i;
+      const int ts = t < c1 ? t : c0;
+      jr[i] = list ? list[ts] : ts;
+      d[i] = coef[ts];
+    }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (ri[u] >= 0) {
-          const int pos = atomicAdd(&cursor[ri[u] >> bin_log], 1);
-          put_ent(ent, pos, (uint32_t)ri[u] & rmask, vv[u] * d);
+    for (int i = 0; i < CPG; ++i) {
+      kb[i] = (int)colptr[jr[i]];
+      ke[i] = (int)colptr[jr[i] + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < CPG; ++i)
+      if (tb + grp + G * i >= c1 || d[i] == (T)0) ke[i] = kb[i];
+    for (int o = 0;; o += 16 * U) {
+      int ri[CPG][U];
+      T vv[CPG][U];
+#pragma unroll
+      for (int i = 0; i < CPG; ++i)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = kb[i] + o + sub + 16 * u;
+          const int kk = k < ke[i] ? k : 0;
+          ri[i][u] = rowidx[kk];
+          vv[i][u] = v[kk];
         }
+      bool left = false;
+#pragma unroll
+      for (int i = 0; i < CPG; ++i) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (kb[i] + o + sub + 16 * u < ke[i]) {
+            const int pos = atomicAdd(&cursor[ri[i][u] >> bin_log], 1);
+            put_ent(ent, pos, (uint32_t)ri[i][u] & rmask, vv[i][u] * d[i]);
+          }
+        left |= kb[i] + o + 16 * U < ke[i];
       }
+      if (!left) break;
     }
   }
 }
@@ -859,17 +885,15 @@ k_bin_acc(const Ent<T>* __restrict__ ent, const int* __restrict__ tot, int bin_l
   for (long long e0 = start + threadIdx.x; e0 < end; e0 += kAccThreads * kAccUnroll) {
     Ent<T> en[kAccUnroll];
 #pragma unroll
-    for (int u = 0; u < kAccUnroll; ++u) {
+    for (int u = 0; u < kAccUnroll; ++u) {  // unconditional loads (past the bin: entry e0)
       const long long e = e0 + (long long)u * kAccThreads;
-      if (e < end) {
-        en[u] = ent[e];
-      } else {
-        en[u].row = 0;
-        en[u].val = (T)0;
-      }
+      en[u] = ent[e < end ? e : e0];
     }
 #pragma unroll
-    for (int u = 0; u < kAccUnroll; ++u) limb_add_val(&cells[(int)en[u].row], R, en[u].val);
+    for (int u = 0; u < kAccUnroll; ++u) {
+      const bool ok = e0 + (long long)u * kAccThreads < end;
+      limb_add_val(&cells[ok ? (int)en[u].row : 0], R, ok ? en[u].val : (T)0);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < R; i += kAccThreads) {
@@ -1206,9 +1230,10 @@ extern "C" sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype,
   p->sparse = true;
   p->nnz = nnz;
   p->ncu = device_cu_count();
-  // bins of R = 2^bin_log rows, at most 128 bins while 64 <= R <= 1024
+  // bins of R = 2^bin_log rows, at most 256 bins while 64 <= R <= 1024 (one accumulation
+  // workgroup per bin: 1e5 rows give 196 bins of 512 rows)
   int lg = kBinMinLog;
-  while (lg < kBinMaxLog && ((int64_t)1 << lg) * 128 < m) ++lg;
+  while (lg < kBinMaxLog && ((int64_t)1 << lg) * 256 < m) ++lg;
   p->bin_log = lg;
   p->bin_nb = (int)((m + ((int64_t)1 << lg) - 1) >> lg);
   p->bin_grid = std::min(kBinGridMax, p->ncu);
