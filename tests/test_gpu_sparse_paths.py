@@ -4,9 +4,11 @@ against the FP64 CPU oracle (scipy.sparse on the oracle side):
 * panel split (at most 16 panels of 140 KiB of r): one workgroup per (panel, chunk of the
   drawn list) writes partial dot products, a second kernel adds them and takes the best
   response; several panels here (m = 50000 FP64, m = 100000 FP32: 3 panels each);
-* panel walk (more than 16 panels: m = 300000 FP64, 17 panels): every workgroup walks all
-  panels of r;
-* gather (more than 2048 row bins of 1024 rows: m = 2.2e6): r read from memory.
+* panel walk (more than 16 panels: m = 300000 FP64 and m = 600000 FP32, 17 panels each):
+  every workgroup walks all panels of r;
+* gather (more than 2048 row bins of 1024 rows: m = 2.2e6): r read from memory;
+
+each in FP64 (iterates) and FP32 (objective and iterates).
 
 The small-m sparse tests elsewhere run the split kernel with a single panel.  Tolerances
 as for the dense path: FP64 1e-10 relative, FP32 objective 1e-4."""
@@ -70,6 +72,23 @@ def test_sparse_gradient_paths_fp64(m, n, per_col, block, p):
     P, _, _, gpu = _run(w, 12, 4)
     for (xg, rg), (xo, ro) in zip(gpu, _oracle_traj(w, prob, 12, 4)):
         assert _rel(xg, xo) <= 1e-10 and _rel(rg, ro) <= 1e-10
+    P.close()
+
+
+@pytest.mark.parametrize("m,n,per_col,block,p", [
+    (600000, 8000, 30, 32, 0.5),      # walk, 17 panels of 35840 rows (FP32)
+    (2200000, 2000, 12, 16, 0.6),     # gather
+])
+def test_sparse_gradient_paths_fp32_objective(m, n, per_col, block, p):
+    w = inputs.sparse_problem(m, n, per_col=per_col, nnz_frac=0.01, lam_frac=0.01, block=block,
+                              p=p, dtype=torch.float32, seed=m % 991)
+    prob = _oracle(w)
+    P, o, x, gpu = _run(w, 12, 4)
+    xo = _oracle_traj(w, prob, 12, 4)[-1][0]
+    Fo = O.objective(prob, xo)
+    Fg = sca.sca_objective(P.handle, o, x)["F"]
+    assert abs(Fg - Fo) <= 1e-4 * abs(Fo)
+    assert _rel(gpu[-1][0], xo) <= 1e-3
     P.close()
 
 
