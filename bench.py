@@ -5,9 +5,9 @@ nonzeros +-[1,2], noise sigma 0.01, lam = 0.01 ||A^T b||_inf, blocks of 64 coord
 25% of blocks drawn per round, gamma 0.9, tau from the random-matrix estimate.
 
 One timed step = one complete solve from x = 0 until the relative objective error
-(F - F*)/|F*| <= 1e-6 (every round: block draw, gradient + best response + step, compaction,
-residual fold; every 10 rounds: FP64 objective; the stop is confirmed with a fresh FP64
-residual).  value = coordinate updates per second over the timed solves; ms_per_step =
+(F - F*)/|F*| <= 1e-6 (every round: block draw, gradient + best response + step and the
+residual fold, at this size one fused kernel plus the reduction of its partials; every 10
+rounds: FP64 objective; the stop is confirmed with a fresh FP64 residual).  value = coordinate updates per second over the timed solves; ms_per_step =
 time to tolerance.  F* comes from an FP64 solve of the same stored data to merit <= 1e-12.
 
 The JSON line also carries the roofline of the dominant kernel (the gradient pass, timed

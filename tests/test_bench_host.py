@@ -1,0 +1,106 @@
+"""Host logic of bench.py (no GPU): the algorithmic byte counts behind the roofline line, the
+kernel names it reports, and the summary of the FETCH_SIZE / WRITE_SIZE counter runs (scaled
+by what the counters read for a copy of known size) with its source fingerprint."""
+import csv
+import importlib.util
+import json
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+FUSED = {"grad_kind": 4, "grad_cols": 1, "grad_unroll": 1, "grad_wg_per_cu": 1}
+TWO_PASS = {"grad_kind": 1, "grad_cols": 4, "grad_unroll": 4, "grad_wg_per_cu": 2}
+
+
+def test_row_groups_per_thread_of_the_fused_round(bench):
+    # 16-byte row groups of an m-row column over 1024 threads
+    assert bench.fused_q(20000, 4) == 5      # 5000 groups
+    assert bench.fused_q(20480, 4) == 5      # 5120 groups: the FP32 limit
+    assert bench.fused_q(20481, 4) == 6
+    assert bench.fused_q(6144, 8) == 3       # the FP64 limit
+    assert bench.fused_q(1, 4) == 1
+
+
+def test_algorithmic_bytes_per_launch(bench):
+    # drawn columns once; the fused round also writes one m-vector of partials per workgroup
+    assert bench.round_alg_bytes(TWO_PASS, 25000, 20000, 4, 256) == 25000 * 20000 * 4
+    assert bench.round_alg_bytes(FUSED, 25000.6, 20000, 4, 256) == pytest.approx(
+        25000.6 * 80000 + 256 * 80000)
+    assert bench.round_alg_bytes(FUSED, 25000.6, 20000, 4, 256) == pytest.approx(2.0206e9,
+                                                                                 rel=1e-4)
+
+
+def test_kernel_names(bench):
+    assert bench.grad_kernel_name(FUSED, False, 20000) == "k_grad_br_fold<float,5,1>"
+    assert bench.grad_kernel_name(dict(FUSED, grad_cols=2), False, 10000) == \
+        "k_grad_br_fold<float,3,2>"
+    assert bench.grad_kernel_name(TWO_PASS, False, 20000) == "k_grad_br_wg<float,4,4,true>"
+
+
+def test_sparse_kernel_names_follow_the_library_panel_limits(bench):
+    """bench.py names the panel-split kernels exactly where the library runs them: r in at
+    most kSplitMaxPanels panels of kSplitPanelBytes (read from the library source)."""
+    src = open(os.path.join(ROOT, "paper_1701_04900_amd", "csrc", "sca_csc.hip")).read()
+    panel_bytes = int(re.search(r"constexpr int kSplitPanelBytes = (\d+);", src).group(1))
+    max_panels = int(re.search(r"constexpr int kSplitMaxPanels = (\d+);", src).group(1))
+    rows = panel_bytes // 4
+    split = "k_dot_split<float,8> + k_br_split<float,8>"
+    assert bench.grad_kernel_name(TWO_PASS, True, 100000) == split
+    assert bench.grad_kernel_name(TWO_PASS, True, rows * max_panels) == split
+    assert bench.grad_kernel_name(TWO_PASS, True, rows * max_panels + 1) == \
+        "k_grad_br_cscp<float,8>"
+
+
+def _counter_dir(root, name, counter, rows):
+    d = os.path.join(root, name, "host", "1")
+    os.makedirs(d)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for kname, val in rows:
+            w.writerow(dict(Kernel_Name=kname, Counter_Name=counter, Counter_Value=val))
+    return os.path.join(root, name)
+
+
+def test_counter_summary_scaling_and_fingerprint(bench, tmp_path, monkeypatch):
+    """Copy of 1 GiB reads 2 GiB of FETCH_SIZE (scale 0.5) and 1 GiB of WRITE_SIZE (scale 1):
+    the kernel's per-launch bytes are its mean KiB x 1024 x scale; the summary is used only
+    while the kernel source and launch shape match its fingerprint."""
+    gib_kib = (1 << 30) / 1024.0
+    kname = "void sca::k_grad_br_fold<float, 5, 1>(float const*, long long, int)"
+    fetch = _counter_dir(str(tmp_path), "fetch", "FETCH_SIZE",
+                         [("k_stream_copy(...)", 2 * gib_kib)] * 3 +
+                         [(kname, 2.0e6), (kname, 2.2e6), ("other_kernel", 5.0)])
+    write = _counter_dir(str(tmp_path), "write", "WRITE_SIZE",
+                         [("k_stream_copy(...)", gib_kib)] * 3 + [(kname, 1.0e4)] * 2)
+    probe = tmp_path / "probe.json"
+    probe.write_text("startup noise\n" + json.dumps(dict(
+        rounds=30, coord_updates=750018, launch=FUSED, m=20000, groups=256)) + "\n")
+    summary = tmp_path / "pmc_summary.txt"
+    monkeypatch.setattr(bench, "PMC_SUMMARY", str(summary))
+    bench.pmc_summarize(fetch, write, str(probe))
+    kv = dict(line.split(": ", 1) for line in summary.read_text().splitlines()
+              if ": " in line and not line.startswith(" "))
+    fetch_b = 2.1e6 * 1024 * 0.5
+    write_b = 1.0e4 * 1024 * 1.0
+    assert float(kv["fetch_bytes_per_launch"]) == pytest.approx(fetch_b, abs=1)
+    assert float(kv["write_bytes_per_launch"]) == pytest.approx(write_b, abs=1)
+    assert float(kv["traffic_bytes_per_launch"]) == pytest.approx(fetch_b + write_b, abs=1)
+    alg = bench.round_alg_bytes(FUSED, 750018 / 30, 20000, 4, 256)
+    assert float(kv["algorithmic_bytes_per_launch"]) == pytest.approx(alg, abs=1)
+    assert int(kv["launches"]) == 2
+    assert kv["fingerprint"].strip() == bench.kernel_fingerprint(FUSED)
+    assert bench.pmc_traffic(FUSED) == pytest.approx(fetch_b + write_b, abs=1)
+    assert bench.pmc_traffic(dict(FUSED, grad_cols=2)) is None  # another launch shape
