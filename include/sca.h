@@ -138,8 +138,8 @@ sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtype, int64_t 
  * SCA_EINVAL.  Device memory: the CSC copy plus a fold workspace of nnz entries (8 bytes
  * each in FP32, 16 in FP64); where r fits in NP <= 16 row panels of 140 KiB (m <= 573440
  * FP32, 286720 FP64), also n x (NP+1) int32 panel offsets and NP x n partial sums of the
- * dtype for the panel-split gradient.  Other arguments as for the dense form.  Synchronises
- * 'stream'. */
+ * dtype for the panel-split gradient (when those do not fit, the slower panel-walk gradient
+ * runs instead).  Other arguments as for the dense form.  Synchronises 'stream'. */
 sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype, int64_t m, int64_t n,
                                   int64_t nnz, const int64_t* rowptr_dev,
                                   const int32_t* colidx_dev, const void* vals_dev,

@@ -1174,17 +1174,22 @@ static sca_status build_csc(sca_problem* p, const long long* rowptr, const int32
 }
 
 // Panel-split gradient set-up: panels of at most kSplitPanelBytes of r; problems that need
-// more than kSplitMaxPanels keep the panel-walk (or gather) gradient.
+// more than kSplitMaxPanels, or whose offsets and partials do not fit in device memory, keep
+// the panel-walk (or gather) gradient.
 static sca_status split_setup(sca_problem* p, hipStream_t s) {
   const int64_t PR = kSplitPanelBytes / (int64_t)p->esize;
   const int64_t NP = (p->m + PR - 1) / PR;
   if (NP < 1 || NP > kSplitMaxPanels) return SCA_OK;
   const int64_t PE = ((p->m + NP - 1) / NP + 63) / 64 * 64;
   const size_t n1 = (size_t)std::max<int64_t>(1, p->n);
-  sca_status st;
-  if ((st = dev_alloc((void**)&p->d_pofs, sizeof(int) * n1 * (size_t)(NP + 1))) != SCA_OK ||
-      (st = dev_alloc(&p->d_sp_part, p->esize * n1 * (size_t)NP)) != SCA_OK)
-    return st;
+  if (dev_alloc((void**)&p->d_pofs, sizeof(int) * n1 * (size_t)(NP + 1)) != SCA_OK ||
+      dev_alloc(&p->d_sp_part, p->esize * n1 * (size_t)NP) != SCA_OK) {
+    if (p->d_pofs) (void)hipFree(p->d_pofs);
+    if (p->d_sp_part) (void)hipFree(p->d_sp_part);
+    p->d_pofs = nullptr;
+    p->d_sp_part = nullptr;
+    return SCA_OK;  // the panel-walk gradient needs neither
+  }
   if (p->n > 0) {
     const int grid = (int)std::min<int64_t>((p->n + 255) / 256, 8 * (int64_t)p->ncu);
     hipLaunchKernelGGL(k_panel_offsets, dim3(grid), dim3(256), 0, s,
