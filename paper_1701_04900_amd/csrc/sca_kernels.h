@@ -247,7 +247,15 @@ static __global__ void __launch_bounds__(1024) k_select(int nblocks, const int* 
   __shared__ int s_off[kSelList];
   __shared__ int s_bp[kSelBp];
   if (nblocks < kSelBp) {
-    for (int i = threadIdx.x; i <= nblocks; i += 1024) s_bp[i] = bp[i];
+    // all loads first (an index past nblocks reads bp[nblocks], not stored), then the stores
+    int v[kSelBp / 1024];
+#pragma unroll
+    for (int u = 0; u < kSelBp / 1024; ++u) v[u] = bp[min((int)threadIdx.x + 1024 * u, nblocks)];
+#pragma unroll
+    for (int u = 0; u < kSelBp / 1024; ++u) {
+      const int i = (int)threadIdx.x + 1024 * u;
+      if (i <= nblocks) s_bp[i] = v[u];
+    }
     __syncthreads();
     select_run(nblocks, (const int*)s_bp, seed, inst, T, st, sel_cols, sh, s_blk, s_off,
                blk_out);
