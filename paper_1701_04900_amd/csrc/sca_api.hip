@@ -621,7 +621,7 @@ static void grad_fold_dense(sca_problem* p, T* x, const T* r_read, const T* base
   prof_begin(p, s, SCA_K_FOLD);
   constexpr int VN = V16<T>::N;
   const int nq = (m + VN - 1) / VN;
-  hipLaunchKernelGGL(k_part_reduce<T>, dim3((nq + 63) / 64), dim3(1024), 0, s,
+  hipLaunchKernelGGL(k_part_reduce<T>, dim3((nq + kPartRows - 1) / kPartRows), dim3(256), 0, s,
                      (const T*)p->d_part, (long long)p->ldp, G, m, base, out, st, fs.on);
   prof_end(p, s, 0.0);
 }

@@ -816,13 +816,15 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
   }
 }
 
-// r[i] = base[i] + sum over w < G of part[w][i] (base may be r): each lane one 16-byte row
-// group, wave v adds the partials [v*G/16, (v+1)*G/16) in order, then the 16 wave sums are
-// added to base in wave order.
+// r[i] = base[i] + sum over w < G of part[w][i] (base may be r).  A 256-thread workgroup
+// takes 16 row groups of 16 bytes; lane group v (16 lanes, one per row group) adds the
+// partials [v*G/16, (v+1)*G/16) in order, then one thread per row group adds the 16 group
+// sums to base in group order (the same order for any grid).
 // With advance != 0 (the block draw ran inside the fused kernel) it also advances the round
 // state the way k_select does: next round, step, drawn-coordinate total.
+constexpr int kPartRows = 16;  // row groups per workgroup of k_part_reduce
 template <typename T>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(256)
 k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, const T* base, T* r,
               RoundState* __restrict__ st, int advance) {
   if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -835,14 +837,14 @@ k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, const T* 
   }
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
-  constexpr int KMAX = 16;  // partials per wave (G <= 256)
-  __shared__ VA sh[16][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = (blockIdx.x * 64 + lane) * VN;
+  constexpr int KMAX = 16;  // partials per lane group (G <= 256)
+  __shared__ VA sh[16][kPartRows];
+  const int rg = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int row = (blockIdx.x * kPartRows + rg) * VN;
   VA acc;
 #pragma unroll
   for (int e = 0; e < VN; ++e) acc[e] = (T)0;
-  const int g0 = wave * G / 16, g1 = (wave + 1) * G / 16;
+  const int g0 = grp * G / 16, g1 = (grp + 1) * G / 16;
   if (row < m && g1 > g0) {
     VA v[KMAX];
 #pragma unroll
@@ -852,19 +854,19 @@ k_part_reduce(const T* __restrict__ part, long long ldp, int G, int m, const T* 
     for (int k = 0; k < KMAX; ++k)
       if (g0 + k < g1) acc += v[k];
   }
-  sh[wave][lane] = acc;
+  sh[grp][rg] = acc;
   __syncthreads();
-  if (wave == 0 && row < m) {
+  if (grp == 0 && row < m) {
     if (row + VN <= m) {
       VA s = *reinterpret_cast<const VA*>(base + row);
 #pragma unroll
-      for (int w = 0; w < 16; ++w) s += sh[w][lane];
+      for (int w = 0; w < 16; ++w) s += sh[w][rg];
       *reinterpret_cast<VA*>(r + row) = s;
     } else {
       for (int e = 0; e < m - row; ++e) {
         T s = base[row + e];
 #pragma unroll
-        for (int w = 0; w < 16; ++w) s += sh[w][lane][e];
+        for (int w = 0; w < 16; ++w) s += sh[w][rg][e];
         r[row + e] = s;
       }
     }
