@@ -386,15 +386,22 @@ def bench_delay(args):
     print(json.dumps(out), flush=True)
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_grad_br_fold_lasso_20000x100000_fp32.txt")
+PMC_SUMMARY = {
+    "lasso": os.path.join(ROOT, "profiles", "pmc_k_grad_br_fold_lasso_20000x100000_fp32.txt"),
+    "sparse": os.path.join(ROOT, "profiles", "pmc_k_dot_split_sparse_lasso_100000x1000000_fp32.txt"),
+}
+# sources whose kernels the counter runs measured (their digest is the summary's fingerprint)
+PMC_SOURCES = {"lasso": ("sca_kernels.h", "sca_device.h"),
+               "sparse": ("sca_kernels.h", "sca_device.h", "sca_csc.hip")}
+SPARSE_STEP_KERNELS = ("k_dot_split<float,8>", "k_br_split<float,8>")
 CALIB_BYTES = 1 << 30
 
 
-def kernel_fingerprint(launch):
+def kernel_fingerprint(launch, kind="lasso"):
     """Digest of the round kernels' source and the launch shape the counters were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sca_kernels.h", "sca_device.h"):
+    for f in PMC_SOURCES[kind]:
         h.update(open(os.path.join(ROOT, "paper_1701_04900_amd", "csrc", f), "rb").read())
     h.update(json.dumps(launch, sort_keys=True).encode())
     return h.hexdigest()[:16]
@@ -402,8 +409,11 @@ def kernel_fingerprint(launch):
 
 def pmc_probe(args):
     """What the counter runs profile: three copies of exactly 1 GiB (the calibration), then
-    30 rounds of the 20000 x 100000 FP32 workload from x = 0."""
-    w = inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")
+    30 rounds from x = 0 of the 20000 x 100000 FP32 LASSO (or, with --workload sparse, of
+    the 1e5 x 1e6 sparse LASSO)."""
+    sparse = args.workload == "sparse"
+    w = (inputs.sparse_lasso_fp32(device="cuda") if sparse else
+         inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda"))
     src = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -414,15 +424,20 @@ def pmc_probe(args):
     o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, max_rounds=30,
                       check_every=10)
     x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
-    st = sca.sca_solve(P.handle, o, x)
-    print(json.dumps(dict(rounds=st["rounds"], coord_updates=st["coord_updates"],
-                          launch=sca.sca_problem_get_launch(P.handle), m=w.m,
-                          groups=fused_groups())), flush=True)
+    st = sca.sca_solve(P.handle, o, x, raise_on_notconv=False)
+    out = dict(workload="sparse" if sparse else "lasso", rounds=st["rounds"],
+               coord_updates=st["coord_updates"], launch=sca.sca_problem_get_launch(P.handle),
+               m=w.m)
+    if sparse:
+        out.update(n=w.n, nnz=w.nnz, per_col=w.nnz // w.n)
+    else:
+        out.update(groups=fused_groups())
+    print(json.dumps(out), flush=True)
 
 
 def pmc_summarize(fetch_dir, write_dir, probe_json):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the calibration copy and of the gradient
-    kernel -> bytes per launch, scaled so the copy reads and writes exactly 1 GiB."""
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the calibration copy and of the measured
+    step's kernels -> bytes per launch, scaled so the copy reads and writes exactly 1 GiB."""
     import csv
     import glob
 
@@ -435,30 +450,46 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
                 out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return out
     probe = json.loads(open(probe_json).read().strip().splitlines()[-1])
+    kind = probe.get("workload", "lasso")
+    if kind == "sparse":
+        wants = SPARSE_STEP_KERNELS
+        title = ("# HBM traffic of the sparse gradient step (k_dot_split + k_br_split), sparse "
+                 "LASSO 100000x1000000 FP32, 1e8 nonzeros (rocprofv3 counters)")
+        flag = " --workload sparse"
+    else:
+        wants = (grad_kernel_name(probe["launch"], False, probe["m"]),)
+        title = ("# HBM traffic of the dominant round kernel, LASSO 20000x100000 FP32 (rocprofv3 "
+                 "counters)")
+        flag = ""
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         vals = load(d, counter)
         copy = [v for k, v in vals.items() if "k_stream_copy" in k][0]
-        want = grad_kernel_name(probe["launch"], False, probe["m"])
-        grad = [v for k, v in vals.items() if want in k.replace(" ", "")][0]
+        per_launch, launches = 0.0, None
+        for want in wants:
+            grad = [v for k, v in vals.items() if want in k.replace(" ", "")][0]
+            per_launch += sum(grad) / len(grad)
+            launches = len(grad) if launches is None else min(launches, len(grad))
         cal = CALIB_BYTES / (sorted(copy)[len(copy) // 2] * 1024.0)
         res[counter] = dict(copy_kib=sorted(copy)[len(copy) // 2], scale=cal,
-                            grad_kib_mean=sum(grad) / len(grad), launches=len(grad))
+                            grad_kib_mean=per_launch, launches=launches)
     launches = res["FETCH_SIZE"]["launches"]
     fetch_b = res["FETCH_SIZE"]["grad_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
     write_b = res["WRITE_SIZE"]["grad_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
-    alg_b = round_alg_bytes(probe["launch"], probe["coord_updates"] / probe["rounds"],
-                            probe["m"], 4, probe.get("groups", 0))
-    fp = kernel_fingerprint(probe["launch"])
+    drawn = probe["coord_updates"] / probe["rounds"]
+    if kind == "sparse":
+        alg_b = drawn * probe["per_col"] * (4 + 4)
+    else:
+        alg_b = round_alg_bytes(probe["launch"], drawn, probe["m"], 4, probe.get("groups", 0))
+    fp = kernel_fingerprint(probe["launch"], kind)
     lines = [
-        "# HBM traffic of the dominant round kernel, LASSO 20000x100000 FP32 (rocprofv3 "
-        "counters)",
+        title,
         "",
         "Commands (repository root, one MI355X; each counter in a run of its own):",
         "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch -- "
-        "python3 bench.py --pmc-probe > <out>/pmc_probe.json",
+        f"python3 bench.py --pmc-probe{flag} > <out>/pmc_probe.json",
         "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write -- "
-        "python3 bench.py --pmc-probe",
+        f"python3 bench.py --pmc-probe{flag}",
         "  python bench.py --pmc-summarize <out>/pmc_fetch <out>/pmc_write "
         "<out>/pmc_probe.json",
         "",
@@ -476,21 +507,21 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
         f"algorithmic_bytes_per_launch: {alg_b:.0f}",
         f"traffic_over_algorithmic: {(fetch_b + write_b) / alg_b:.4f}",
     ]
-    open(PMC_SUMMARY, "w").write("\n".join(lines) + "\n")
+    open(PMC_SUMMARY[kind], "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def pmc_traffic(launch):
+def pmc_traffic(launch, kind="lasso"):
     """Traffic per launch from the committed counter summary, or None when it is absent or
     was taken on other kernel code or another launch shape."""
-    if not os.path.exists(PMC_SUMMARY):
+    if not os.path.exists(PMC_SUMMARY[kind]):
         return None
     kv = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(PMC_SUMMARY[kind]):
         if ": " in line and not line.startswith(" "):
             k, v = line.split(": ", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("fingerprint") != kernel_fingerprint(launch):
+    if kv.get("fingerprint") != kernel_fingerprint(launch, kind):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -762,7 +793,7 @@ def bench_single(args):
                           "k_bin_scan<4> + k_bin_scatter<float,8> + k_bin_acc<float,float,float>"))
         step, kp, kb, kname = max(cands, key=lambda c: c[1]["ms"])
         achieved = kb / (kp["ms"] * 1e-3) / 1e9
-        traffic = pmc_traffic(L) if kind == "lasso" and step == "grad" else None
+        traffic = pmc_traffic(L, kind) if kind in PMC_SUMMARY and step == "grad" else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic),

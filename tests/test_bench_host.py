@@ -89,7 +89,7 @@ def test_counter_summary_scaling_and_fingerprint(bench, tmp_path, monkeypatch):
     probe.write_text("startup noise\n" + json.dumps(dict(
         rounds=30, coord_updates=750018, launch=FUSED, m=20000, groups=256)) + "\n")
     summary = tmp_path / "pmc_summary.txt"
-    monkeypatch.setattr(bench, "PMC_SUMMARY", str(summary))
+    monkeypatch.setitem(bench.PMC_SUMMARY, "lasso", str(summary))
     bench.pmc_summarize(fetch, write, str(probe))
     kv = dict(line.split(": ", 1) for line in summary.read_text().splitlines()
               if ": " in line and not line.startswith(" "))
@@ -104,3 +104,35 @@ def test_counter_summary_scaling_and_fingerprint(bench, tmp_path, monkeypatch):
     assert kv["fingerprint"].strip() == bench.kernel_fingerprint(FUSED)
     assert bench.pmc_traffic(FUSED) == pytest.approx(fetch_b + write_b, abs=1)
     assert bench.pmc_traffic(dict(FUSED, grad_cols=2)) is None  # another launch shape
+
+
+def test_sparse_counter_summary_adds_both_step_kernels(bench, tmp_path, monkeypatch):
+    """The sparse gradient step is two kernels: their per-launch bytes are added; the
+    algorithmic bytes are (4 B value + 4 B row) per nonzero of the drawn columns."""
+    gib_kib = (1 << 30) / 1024.0
+    dot = "void (anonymous namespace)::k_dot_split<float, 8>(int const*, int const*)"
+    br = "void (anonymous namespace)::k_br_split<float, 8>(long long const*, int const*)"
+    fetch = _counter_dir(str(tmp_path), "fetch", "FETCH_SIZE",
+                         [("k_stream_copy(...)", 2 * gib_kib)] * 3 +
+                         [(dot, 8.0e4)] * 3 + [(br, 1.0e3)] * 3)
+    write = _counter_dir(str(tmp_path), "write", "WRITE_SIZE",
+                         [("k_stream_copy(...)", gib_kib)] * 3 + [(dot, 1.2e3)] * 3 +
+                         [(br, 0.8e3)] * 3)
+    launch = dict(TWO_PASS)
+    probe = tmp_path / "probe.json"
+    probe.write_text(json.dumps(dict(workload="sparse", rounds=30, coord_updates=3000000,
+                                     launch=launch, m=100000, n=1000000, nnz=100000000,
+                                     per_col=100)) + "\n")
+    summary = tmp_path / "pmc_sparse.txt"
+    monkeypatch.setitem(bench.PMC_SUMMARY, "sparse", str(summary))
+    bench.pmc_summarize(fetch, write, str(probe))
+    kv = dict(line.split(": ", 1) for line in summary.read_text().splitlines()
+              if ": " in line and not line.startswith(" "))
+    fetch_b = (8.0e4 + 1.0e3) * 1024 * 0.5
+    write_b = (1.2e3 + 0.8e3) * 1024
+    assert float(kv["traffic_bytes_per_launch"]) == pytest.approx(fetch_b + write_b, abs=1)
+    assert float(kv["algorithmic_bytes_per_launch"]) == pytest.approx(1e5 * 100 * 8, abs=1)
+    assert int(kv["launches"]) == 3
+    assert bench.pmc_traffic(launch, "sparse") == pytest.approx(fetch_b + write_b, abs=1)
+    assert bench.pmc_traffic(launch, "lasso") is None  # the dense summary, another shape
+    assert "--pmc-probe --workload sparse" in summary.read_text()
