@@ -337,6 +337,8 @@ def merit(prob: Problem, x, tau) -> float:
 
 
 def nnz_best_response(prob: Problem, x, tau) -> int:
+    """Number of nonzero coordinates of the best response x_hat(x) (not of x): the
+    soft-threshold yields exact zeros, so this is the support size the method reports."""
     x = np.asarray(x, dtype=np.float64)
     r = residual(prob, x)
     return int(np.count_nonzero(best_response(prob, x, r, np.arange(prob.n), tau)))
@@ -383,26 +385,43 @@ def run_rounds(prob: Problem, cfg: RunConfig, x, r, k0: int, nrounds: int, trace
 
 
 def solve(prob: Problem, cfg: RunConfig, x0=None, max_rounds=100000, check_every=10,
-          F_star=None, tol_rel_obj=None, tol_merit=None):
-    """Run from x0 (default 0) until the relative objective error (F - F*)/|F*|
-    (with a fresh residual) or the merit drops below its tolerance, or max_rounds.
+          F_star=None, tol_rel_obj=None, tol_merit=None, refresh_every=0):
+    """Run from x0 (default 0) until the relative objective error (F - F*)/|F*| or the
+    merit drops below its tolerance, or max_rounds.  A check comes after every
+    check_every rounds (fewer for the last one).  At check number t (counted from 1)
+    with refresh_every > 0 dividing t, the running residual is replaced by a fresh
+    r = Ax - b before the objective is taken (the optional residual refresh: the
+    paper keeps no residual, so this is a reading of ours).  A tolerance on the
+    relative error is tested with the running residual first and confirmed with a
+    fresh one; when the fresh one does not confirm it, the running residual is
+    restarted from the fresh one.
     Returns dict(x, r, rounds, updates, F, history)."""
     x = np.zeros(prob.n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     r = residual(prob, x)
     k = 0
+    checks = 0
     updates = 0
     hist = []
     while k < max_rounds:
         step = min(check_every, max_rounds - k)
         x, r, u = run_rounds(prob, cfg, x, r, k, step)
         k += step
+        checks += 1
         updates += u
+        if refresh_every > 0 and checks % refresh_every == 0:
+            r = residual(prob, x)
         F = objective(prob, x, r)
         hist.append((k, F))
+        done = False
         if tol_rel_obj is not None and F_star is not None:
-            if (objective(prob, x) - F_star) / abs(F_star) <= tol_rel_obj:
-                break
-        if tol_merit is not None and merit(prob, x, cfg.tau) <= tol_merit:
+            if (F - F_star) / abs(F_star) <= tol_rel_obj:
+                fresh = residual(prob, x)
+                done = (objective(prob, x, fresh) - F_star) / abs(F_star) <= tol_rel_obj
+                if not done:
+                    r = fresh
+        if not done and tol_merit is not None:
+            done = merit(prob, x, cfg.tau) <= tol_merit
+        if done:
             break
     return dict(x=x, r=r, rounds=k, updates=updates, F=objective(prob, x), history=hist)
 
