@@ -162,12 +162,52 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dptr(t):
+def _check_buf(t, name, dtype=None, numel=None):
+    """The checks the C ABI cannot make: a dense (contiguous) buffer of the expected dtype
+    holding at least ``numel`` elements."""
     if t is None:
-        return None
-    if not t.is_cuda:
-        raise ValueError("expected a device tensor")
-    return ctypes.c_void_p(t.data_ptr())
+        return
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {numel} needed")
+
+
+def _dptrs(*specs):
+    """Device pointers of (tensor, name, dtype, numel) specs: every buffer is checked with
+    _check_buf first, then each must live on the device (None passes as NULL)."""
+    for sp in specs:
+        _check_buf(*sp)
+    out = []
+    for t, name, *_ in specs:
+        if t is not None and not t.is_cuda:
+            raise ValueError(f"{name}: expected a device tensor")
+        out.append(None if t is None else ctypes.c_void_p(t.data_ptr()))
+    return tuple(out)
+
+
+def _dptr(t, name="buffer", dtype=None, numel=None):
+    """Device pointer of one tensor after the checks of _check_buf."""
+    return _dptrs((t, name, dtype, numel))[0]
+
+
+# Shapes of the live handles created through this module (handle value -> dict), so that
+# the buffers passed with a handle can be checked against its dtype and sizes before the
+# call: the library sees plain pointers and cannot check their extent.
+_SHAPES: dict = {}
+
+
+def _shape(h):
+    v = h.value if isinstance(h, ctypes.c_void_p) else h
+    return _SHAPES.get(v, {})
+
+
+def _forget(h):
+    _SHAPES.pop(h.value if isinstance(h, ctypes.c_void_p) else h, None)
 
 
 def _dtype_code(dt):
@@ -230,22 +270,29 @@ def sca_version():
 def sca_problem_create_dense(At, m, b, lam, c, beta, block_ptr, stream=None):
     """At: (n, lda) device tensor (column-major A), b: (m,) device tensor."""
     n, lda = At.shape
+    code = _dtype_code(At.dtype)
+    pa, pb = _dptrs((At, "At", None, None), (b, "b", At.dtype, m))
     bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
     h = ctypes.c_void_p()
     _check(lib().sca_problem_create_dense(
-        ctypes.byref(h), _dtype_code(At.dtype), m, n, _dptr(At), lda, _dptr(b), float(lam),
+        ctypes.byref(h), code, m, n, pa, lda, pb, float(lam),
         float(c), float(beta), bp.ctypes.data_as(ctypes.POINTER(_I64)), len(bp) - 1,
         _stream(stream)))
+    _SHAPES[h.value] = dict(dtype=At.dtype, m=m, n=n, nblocks=len(bp) - 1)
     return h
 
 
 def sca_problem_create_csr(m, n, rowptr, colidx, vals, b, lam, c, beta, block_ptr, stream=None):
+    code = _dtype_code(vals.dtype)
+    nnz = vals.numel()
+    ptrs = _dptrs((rowptr, "rowptr", torch.int64, m + 1), (colidx, "colidx", torch.int32, nnz),
+                  (vals, "vals", None, None), (b, "b", vals.dtype, m))
     bp = np.ascontiguousarray(block_ptr, dtype=np.int64)
     h = ctypes.c_void_p()
     _check(lib().sca_problem_create_csr(
-        ctypes.byref(h), _dtype_code(vals.dtype), m, n, vals.numel(), _dptr(rowptr),
-        _dptr(colidx), _dptr(vals), _dptr(b), float(lam), float(c), float(beta),
+        ctypes.byref(h), code, m, n, nnz, *ptrs, float(lam), float(c), float(beta),
         bp.ctypes.data_as(ctypes.POINTER(_I64)), len(bp) - 1, _stream(stream)))
+    _SHAPES[h.value] = dict(dtype=vals.dtype, m=m, n=n, nblocks=len(bp) - 1)
     return h
 
 
@@ -254,24 +301,35 @@ def sca_problem_set_regularizer(h, reg, theta=0.0):
 
 
 def sca_problem_update_rhs(h, b, lam, stream=None):
-    _check(lib().sca_problem_update_rhs(h, _dptr(b), float(lam), _stream(stream)))
+    sh = _shape(h)
+    pb = _dptr(b, "b", sh.get("dtype"), sh.get("m"))
+    _check(lib().sca_problem_update_rhs(h, pb, float(lam), _stream(stream)))
 
 
 def sca_problem_destroy(h):
+    _forget(h)
     lib().sca_problem_destroy(h)
 
 
+def _xr(h, x, r):
+    sh = _shape(h)
+    return _dptrs((x, "x", sh.get("dtype"), sh.get("n")), (r, "r", sh.get("dtype"), sh.get("m")))
+
+
 def sca_step(h, opts, round_begin, nrounds, x, r, stream=None):
-    _check(lib().sca_step(h, ctypes.byref(opts), int(round_begin), int(nrounds), _dptr(x),
-                          _dptr(r), _stream(stream)))
+    px, pr = _xr(h, x, r)
+    _check(lib().sca_step(h, ctypes.byref(opts), int(round_begin), int(nrounds), px, pr,
+                          _stream(stream)))
 
 
 def sca_residual(h, x, r, stream=None):
-    _check(lib().sca_residual(h, _dptr(x), _dptr(r), _stream(stream)))
+    px, pr = _xr(h, x, r)
+    _check(lib().sca_residual(h, px, pr, _stream(stream)))
 
 
 def sca_select_blocks(h, opts, k, mask, stream=None):
-    _check(lib().sca_select_blocks(h, ctypes.byref(opts), int(k), _dptr(mask), _stream(stream)))
+    pm = _dptr(mask, "mask", torch.uint8, _shape(h).get("nblocks"))
+    _check(lib().sca_select_blocks(h, ctypes.byref(opts), int(k), pm, _stream(stream)))
 
 
 def sca_philox4x32_10(inp, out, count, stream=None):
@@ -280,7 +338,9 @@ def sca_philox4x32_10(inp, out, count, stream=None):
 
 def sca_objective(h, opts, x, stream=None):
     F, mer, mf, nnz = _D(), _D(), _D(), _I64()
-    _check(lib().sca_objective(h, ctypes.byref(opts), _dptr(x), ctypes.byref(F), ctypes.byref(mer),
+    sh = _shape(h)
+    px = _dptr(x, "x", sh.get("dtype"), sh.get("n"))
+    _check(lib().sca_objective(h, ctypes.byref(opts), px, ctypes.byref(F), ctypes.byref(mer),
                                ctypes.byref(mf), ctypes.byref(nnz), _stream(stream)))
     return dict(F=F.value, merit=mer.value, MF=mf.value, nnz=nnz.value)
 
@@ -288,7 +348,9 @@ def sca_objective(h, opts, x, stream=None):
 def sca_solve(h, opts, x, stream=None, raise_on_notconv=True):
     st = sca_stats()
     st.struct_size = ctypes.sizeof(sca_stats)
-    status = lib().sca_solve(h, ctypes.byref(opts), _dptr(x), ctypes.byref(st), _stream(stream))
+    sh = _shape(h)
+    px = _dptr(x, "x", sh.get("dtype"), sh.get("n"))
+    status = lib().sca_solve(h, ctypes.byref(opts), px, ctypes.byref(st), _stream(stream))
     if status != SCA_OK and not (status == SCA_ENOTCONV and not raise_on_notconv):
         _check(status)
     return st.as_dict()
@@ -296,7 +358,10 @@ def sca_solve(h, opts, x, stream=None, raise_on_notconv=True):
 
 def sca_adjoint(h, opts, xstar, xbar, bbar, cg_tol=0.0, cg_maxit=0, stream=None):
     lb = _D()
-    _check(lib().sca_adjoint(h, ctypes.byref(opts), _dptr(xstar), _dptr(xbar), _dptr(bbar),
+    sh = _shape(h)
+    dt, n, m = sh.get("dtype"), sh.get("n"), sh.get("m")
+    ptrs = _dptrs((xstar, "xstar", dt, n), (xbar, "xbar", dt, n), (bbar, "bbar", dt, m))
+    _check(lib().sca_adjoint(h, ctypes.byref(opts), *ptrs,
                              ctypes.byref(lb), float(cg_tol), int(cg_maxit), _stream(stream)))
     return lb.value
 
@@ -348,6 +413,12 @@ class Problem:
                            w.block_ptr, stream)
         return cls.dense(w.At, w.m, w.b, w.lam, w.c, w.beta, w.block_ptr, stream)
 
+    def update_rhs(self, b, lam, stream=None):
+        """Install a new right-hand side and lambda; b is borrowed, so it is kept alive here
+        for as long as it is the problem's."""
+        sca_problem_update_rhs(self.handle, b, lam, stream)
+        self._keep = (self._keep[0], b) if len(self._keep) == 2 else (b,)
+
     def close(self):
         if self.handle is not None:
             sca_problem_destroy(self.handle)
@@ -367,6 +438,7 @@ def sca_batch_create(items, dtype, stream=None):
     arr = (sca_batch_item * len(items))()
     keep = []
     for k, it in enumerate(items):
+        _dptrs((it["At"], f"At[{k}]", dtype, None), (it["b"], f"b[{k}]", dtype, it["m"]))
         bp = np.ascontiguousarray(it["block_ptr"], dtype=np.int64)
         keep.append(bp)
         arr[k] = sca_batch_item(ctypes.sizeof(sca_batch_item), it["m"], it["n"],
@@ -379,11 +451,20 @@ def sca_batch_create(items, dtype, stream=None):
     h = ctypes.c_void_p()
     _check(lib().sca_batch_create(ctypes.byref(h), _dtype_code(dtype), len(items), arr,
                                   _stream(stream)))
+    xo, ro = sca_batch_layout(h, len(items))
+    _SHAPES[h.value] = dict(dtype=dtype, K=len(items), x=int(xo[-1]), r=int(ro[-1]))
     return h
 
 
 def sca_batch_destroy(h):
+    _forget(h)
     lib().sca_batch_destroy(h)
+
+
+def _bxr(h, x, r):
+    sh = _shape(h)
+    return _dptrs((x, "x_all", sh.get("dtype"), sh.get("x")),
+                  (r, "r_all", sh.get("dtype"), sh.get("r")))
 
 
 def sca_batch_layout(h, K):
@@ -403,19 +484,20 @@ def sca_batch_set_fstar(h, F_star):
 
 
 def sca_batch_residual(h, x_all, r_all, stream=None):
-    _check(lib().sca_batch_residual(h, _dptr(x_all), _dptr(r_all), _stream(stream)))
+    _check(lib().sca_batch_residual(h, *_bxr(h, x_all, r_all), _stream(stream)))
 
 
 def sca_batch_step(h, opts, round_begin, nrounds, x_all, r_all, stream=None):
     _check(lib().sca_batch_step(h, ctypes.byref(opts), int(round_begin), int(nrounds),
-                                _dptr(x_all), _dptr(r_all), _stream(stream)))
+                                *_bxr(h, x_all, r_all), _stream(stream)))
 
 
 def sca_batch_solve(h, opts, x_all, K, stream=None, raise_on_notconv=True):
     st = (sca_stats * K)()
     for k in range(K):
         st[k].struct_size = ctypes.sizeof(sca_stats)
-    status = lib().sca_batch_solve(h, ctypes.byref(opts), _dptr(x_all), st, _stream(stream))
+    px = _bxr(h, x_all, None)[0]
+    status = lib().sca_batch_solve(h, ctypes.byref(opts), px, st, _stream(stream))
     if status != SCA_OK and not (status == SCA_ENOTCONV and not raise_on_notconv):
         _check(status)
     return [st[k].as_dict() for k in range(K)]
@@ -423,24 +505,31 @@ def sca_batch_solve(h, opts, x_all, K, stream=None, raise_on_notconv=True):
 
 def sca_batch_objective(h, opts, x_all, K, stream=None):
     F, mer, mf, nnz = (_D * K)(), (_D * K)(), (_D * K)(), (_I64 * K)()
-    _check(lib().sca_batch_objective(h, ctypes.byref(opts), _dptr(x_all), F, mer, mf, nnz,
-                                     _stream(stream)))
+    _check(lib().sca_batch_objective(h, ctypes.byref(opts), _bxr(h, x_all, None)[0], F, mer,
+                                     mf, nnz, _stream(stream)))
     return dict(F=np.array(F[:]), merit=np.array(mer[:]), MF=np.array(mf[:]),
                 nnz=np.array(nnz[:]))
 
 
 def sca_batch_update_rhs(h, b_all, lam, stream=None):
+    sh = _shape(h)
     a = np.ascontiguousarray(lam, dtype=np.float64)
-    _check(lib().sca_batch_update_rhs(h, _dptr(b_all), a.ctypes.data_as(ctypes.POINTER(_D)),
+    if "K" in sh and a.shape != (sh["K"],):
+        raise ValueError(f"lam: one value per instance ({sh['K']}) expected")
+    pb = _dptr(b_all, "b_all", sh.get("dtype"), sh.get("r"))
+    _check(lib().sca_batch_update_rhs(h, pb, a.ctypes.data_as(ctypes.POINTER(_D)),
                                       _stream(stream)))
 
 
 def sca_batch_adjoint(h, opts, xstar_all, xbar_all, bbar_all, K, cg_tol=0.0, cg_maxit=0,
                       stream=None):
     lb = (_D * K)()
-    _check(lib().sca_batch_adjoint(h, ctypes.byref(opts), _dptr(xstar_all), _dptr(xbar_all),
-                                   _dptr(bbar_all), lb, float(cg_tol), int(cg_maxit),
-                                   _stream(stream)))
+    sh = _shape(h)
+    dt, nx, nr = sh.get("dtype"), sh.get("x"), sh.get("r")
+    ptrs = _dptrs((xstar_all, "xstar_all", dt, nx), (xbar_all, "xbar_all", dt, nx),
+                  (bbar_all, "bbar_all", dt, nr))
+    _check(lib().sca_batch_adjoint(h, ctypes.byref(opts), *ptrs, lb, float(cg_tol),
+                                   int(cg_maxit), _stream(stream)))
     return np.array(lb[:])
 
 
@@ -483,15 +572,19 @@ def sca_multi_create(At, m, B, lams, c=0.0, beta=math.inf, block_ptr=None, strea
     la = np.ascontiguousarray(lams, dtype=np.float64)
     if la.shape != (K,):
         raise ValueError("one lambda per right-hand side")
+    code = _dtype_code(At.dtype)
+    pa, pB = _dptrs((At, "At", None, None), (B, "B", At.dtype, None))
     h = ctypes.c_void_p()
-    _check(lib().sca_multi_create(ctypes.byref(h), _dtype_code(At.dtype), m, n, _dptr(At), lda,
-                                  K, _dptr(B), ldb, la.ctypes.data_as(ctypes.POINTER(_D)),
+    _check(lib().sca_multi_create(ctypes.byref(h), code, m, n, pa, lda,
+                                  K, pB, ldb, la.ctypes.data_as(ctypes.POINTER(_D)),
                                   float(c), float(beta), bp.ctypes.data_as(ctypes.POINTER(_I64)),
                                   len(bp) - 1, _stream(stream)))
+    _SHAPES[h.value] = dict(dtype=At.dtype, K=K, x=K * n, r=K * lda)
     return h
 
 
 def sca_multi_destroy(h):
+    _forget(h)
     lib().sca_multi_destroy(h)
 
 
@@ -501,17 +594,17 @@ def sca_multi_set_fstar(h, F_star):
 
 
 def sca_multi_residual(h, X, R, stream=None):
-    _check(lib().sca_multi_residual(h, _dptr(X), _dptr(R), _stream(stream)))
+    _check(lib().sca_multi_residual(h, *_bxr(h, X, R), _stream(stream)))
 
 
 def sca_multi_step(h, opts, round_begin, nrounds, X, R, stream=None):
-    _check(lib().sca_multi_step(h, ctypes.byref(opts), round_begin, nrounds, _dptr(X), _dptr(R),
+    _check(lib().sca_multi_step(h, ctypes.byref(opts), round_begin, nrounds, *_bxr(h, X, R),
                                 _stream(stream)))
 
 
 def sca_multi_objective(h, opts, X, K, stream=None):
     F, mer, nnz = (_D * K)(), (_D * K)(), (_I64 * K)()
-    _check(lib().sca_multi_objective(h, ctypes.byref(opts), _dptr(X), F, mer, nnz,
+    _check(lib().sca_multi_objective(h, ctypes.byref(opts), _bxr(h, X, None)[0], F, mer, nnz,
                                      _stream(stream)))
     return dict(F=np.array(F[:]), merit=np.array(mer[:]), nnz=np.array(nnz[:]))
 
@@ -520,7 +613,8 @@ def sca_multi_solve(h, opts, X, K, stream=None, raise_on_notconv=True):
     st = (sca_stats * K)()
     for k in range(K):
         st[k].struct_size = ctypes.sizeof(sca_stats)
-    status = lib().sca_multi_solve(h, ctypes.byref(opts), _dptr(X), st, _stream(stream))
+    status = lib().sca_multi_solve(h, ctypes.byref(opts), _bxr(h, X, None)[0], st,
+                                   _stream(stream))
     if status != SCA_OK and not (status == SCA_ENOTCONV and not raise_on_notconv):
         _check(status)
     return [st[k].as_dict() for k in range(K)]
@@ -570,17 +664,22 @@ class SolveFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, b, lam, problem, opts):
-        sca_problem_update_rhs(problem.handle, b, float(lam))
+        b = b.detach().contiguous()
+        lam = float(lam)
+        problem.update_rhs(b, lam)
         x = torch.zeros(problem.n, dtype=problem.dtype, device=b.device)
         sca_solve(problem.handle, opts, x)
         ctx.save_for_backward(x)
         ctx.problem, ctx.opts = problem, opts
-        ctx.keep_b = b
+        ctx.b, ctx.lam = b, lam
         return x
 
     @staticmethod
     def backward(ctx, xbar):
         (x,) = ctx.saved_tensors
+        # the handle may have been given another (b, lam) by a later forward: the adjoint
+        # takes the support and residual from the problem, so this forward's are restored
+        ctx.problem.update_rhs(ctx.b, ctx.lam)
         bbar = torch.empty(ctx.problem.m, dtype=ctx.problem.dtype, device=x.device)
         lb = sca_adjoint(ctx.problem.handle, ctx.opts, x, xbar.contiguous(), bbar)
         return bbar, torch.tensor(lb, dtype=torch.float64, device=x.device), None, None
@@ -591,17 +690,23 @@ class BatchSolveFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, b_all, lam, batch, opts):
-        sca_batch_update_rhs(batch.handle, b_all, lam.detach().double().cpu().numpy())
+        b_all = b_all.detach().contiguous()
+        lam_host = lam.detach().double().cpu().numpy().copy()
+        sca_batch_update_rhs(batch.handle, b_all, lam_host)
         x = torch.zeros(int(batch.xoff[-1]), dtype=batch.dtype, device=b_all.device)
         sca_batch_solve(batch.handle, opts, x, batch.K)
         ctx.save_for_backward(x)
         ctx.batch, ctx.opts = batch, opts
+        ctx.b_all, ctx.lam, ctx.lam_device = b_all, lam_host, lam.device
         return x
 
     @staticmethod
     def backward(ctx, xbar):
         (x,) = ctx.saved_tensors
+        # restore this forward's right-hand sides and weights (a later forward may have
+        # replaced them; the batch copies b, so the saved tensor is what is re-installed)
+        sca_batch_update_rhs(ctx.batch.handle, ctx.b_all, ctx.lam)
         bbar = torch.zeros(int(ctx.batch.roff[-1]), dtype=ctx.batch.dtype, device=x.device)
         lb = sca_batch_adjoint(ctx.batch.handle, ctx.opts, x, xbar.contiguous(), bbar,
                                ctx.batch.K)
-        return bbar, torch.as_tensor(lb, dtype=torch.float64, device=x.device), None, None
+        return bbar, torch.as_tensor(lb, dtype=torch.float64, device=ctx.lam_device), None, None

@@ -136,6 +136,71 @@ def test_autograd_function_gives_the_adjoint():
     assert abs(float(gl) - lb) <= 1e-12 * max(1, abs(lb))
 
 
+def test_autograd_backward_after_a_second_forward_on_the_same_problem():
+    """Two forwards on one Problem (two right-hand sides and weights), then the first
+    backward: it must be the adjoint at the first (b, lam), not at the (b, lam) the handle
+    held last.  The first b is a temporary, released by the caller after the forward."""
+    w = inputs.dense_problem(150, 400, nnz_frac=0.05, lam_frac=0.1, block=8, p=1.0,
+                             dtype=torch.float64, seed=24)
+    wd = w.to("cuda")
+    P = sca.Problem.from_workload(wd)
+    o = _tight(w)
+    rng = np.random.default_rng(8)
+    b1 = (wd.b + 0.05 * torch.from_numpy(rng.normal(size=w.m)).cuda()).requires_grad_(True)
+    lam1 = torch.tensor(w.lam * 1.3, dtype=torch.float64, requires_grad=True)
+    x1 = sca.SolveFn.apply(b1 * 1.0, lam1, P, o)  # b1 * 1.0: a temporary the caller drops
+    b2 = wd.b.clone().requires_grad_(True)
+    lam2 = torch.tensor(w.lam * 0.7, dtype=torch.float64, requires_grad=True)
+    x2 = sca.SolveFn.apply(b2, lam2, P, o)
+    assert float((x1 - x2).abs().max()) > 1e-3  # the two solutions differ
+    wvec = torch.linspace(-1, 1, w.n, dtype=torch.float64, device="cuda")
+    g1b, g1l = torch.autograd.grad((wvec * x1).sum(), (b1, lam1))
+    # reference: a problem of its own at the first (b, lam)
+    bref = b1.detach().clone()
+    Q = sca.Problem.dense(wd.At, w.m, bref, float(lam1), block_ptr=w.block_ptr)
+    bbar = torch.empty(w.m, dtype=torch.float64, device="cuda")
+    lb = sca.sca_adjoint(Q.handle, o, x1.detach(), wvec, bbar)
+    assert torch.allclose(g1b, bbar, rtol=0, atol=1e-12)
+    assert abs(float(g1l) - lb) <= 1e-12 * max(1, abs(lb))
+    # and the second backward is still the adjoint at the second (b, lam)
+    g2b, g2l = torch.autograd.grad((wvec * x2).sum(), (b2, lam2))
+    R = sca.Problem.dense(wd.At, w.m, b2.detach().clone(), float(lam2), block_ptr=w.block_ptr)
+    lb2 = sca.sca_adjoint(R.handle, o, x2.detach(), wvec, bbar)
+    assert torch.allclose(g2b, bbar, rtol=0, atol=1e-12)
+    assert abs(float(g2l) - lb2) <= 1e-12 * max(1, abs(lb2))
+    Q.close()
+    R.close()
+    P.close()
+
+
+def test_batch_autograd_backward_after_a_second_forward():
+    ws = inputs.batch_lasso(3, m_range=(80, 200), nnz_frac=0.05, lam_range=(3e-2, 1.5e-1),
+                            block=8, p=0.5, dtype=torch.float64, seed=29)
+    wd = [w.to("cuda") for w in ws]
+    B = sca.Batch(wd)
+    o = sca.make_opts(gamma=0.9, select_p=0.5, seed=3, max_rounds=50000, check_every=20,
+                      tol_merit=1e-13)
+    b_all = torch.zeros(int(B.roff[-1]), dtype=torch.float64, device="cuda")
+    for k, w in enumerate(wd):
+        b_all[B.roff[k]:B.roff[k] + w.m] = w.b
+    lam1 = torch.tensor([w.lam for w in ws], dtype=torch.float64, requires_grad=True)
+    b1 = b_all.clone().requires_grad_(True)
+    x1 = sca.BatchSolveFn.apply(b1, lam1, B, o)
+    lam2 = (lam1.detach() * 0.6).requires_grad_(True)
+    b2 = (b_all * 1.1).requires_grad_(True)
+    x2 = sca.BatchSolveFn.apply(b2, lam2, B, o)
+    assert float((x1 - x2).abs().max()) > 1e-3
+    wvec = torch.linspace(-1, 1, int(B.xoff[-1]), dtype=torch.float64, device="cuda")
+    g1b, g1l = torch.autograd.grad((wvec * x1).sum(), (b1, lam1))
+    # reference: the batch adjoint with the first right-hand sides installed explicitly
+    sca.sca_batch_update_rhs(B.handle, b_all, lam1.detach().numpy())
+    bbar = torch.zeros(int(B.roff[-1]), dtype=torch.float64, device="cuda")
+    lbs = sca.sca_batch_adjoint(B.handle, o, x1.detach(), wvec, bbar, B.K)
+    assert torch.allclose(g1b, bbar, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g1l.numpy(), lbs, rtol=1e-12, atol=1e-12)
+    B.close()
+
+
 def test_adjoint_rejects_dc_and_sparse():
     w = inputs.dense_problem(60, 120, nnz_frac=0.05, lam_frac=0.1, block=4, p=1.0,
                              dtype=torch.float64, seed=25).to("cuda")
