@@ -130,7 +130,8 @@ sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtype, int64_t 
                                     double lambda, double c, double beta,
                                     const int64_t* block_ptr_host, int64_t nblocks, void* stream);
 
-/* Create a problem over a sparse A given in CSR (row-major) form: rowptr_dev (m+1 int64),
+/* Create a problem over a sparse A given in CSR (row-major) form (the sparse LASSO data of
+ * the paper's Section 4.2 experiments; problem (1) with f = 1/2||Ax - b||^2): rowptr_dev (m+1 int64),
  * colidx_dev (nnz int32 in [0,n)), vals_dev (nnz of the dtype), b_dev (m).  The library
  * builds and owns a column-major (CSC) copy with rows ascending inside each column; the
  * caller may free the CSR once this call returns.  Limits: 0 <= nnz < 2^31, m <= 2^23
@@ -139,7 +140,11 @@ sca_status sca_problem_create_dense(sca_problem** out, sca_dtype dtype, int64_t 
  * each in FP32, 16 in FP64); where r fits in NP <= 16 row panels of 140 KiB (m <= 573440
  * FP32, 286720 FP64), also n x (NP+1) int32 panel offsets and NP x n partial sums of the
  * dtype for the panel-split gradient (when those do not fit, the slower panel-walk gradient
- * runs instead).  Other arguments as for the dense form.  Synchronises 'stream'. */
+ * runs instead).  Other arguments as for the dense form.  Synchronises 'stream'.
+ * The residual fold of a sparse problem sums the products a_ij * dx_j of a row exactly in
+ * fixed point: each product and each row's sum must stay below 2^55 in magnitude; a row
+ * that receives a larger or non-finite product becomes NaN, so the next objective check
+ * of sca_solve returns SCA_ENONFINITE. */
 sca_status sca_problem_create_csr(sca_problem** out, sca_dtype dtype, int64_t m, int64_t n,
                                   int64_t nnz, const int64_t* rowptr_dev,
                                   const int32_t* colidx_dev, const void* vals_dev,
@@ -163,7 +168,10 @@ void sca_problem_destroy(sca_problem* p);
 sca_status sca_step(sca_problem* p, const sca_opts* opts, int64_t round_begin, int64_t nrounds,
                     void* x_dev, void* r_dev, void* stream);
 
-/* r_dev <- A x_dev - b with FP64 accumulation, rounded to the dtype.  Stream-ordered. */
+/* r_dev <- A x_dev - b with FP64 accumulation, rounded to the dtype: the residual the
+ * partial gradients of Algorithm 1 step S.2 read (a_j^T r is the partial gradient of
+ * 1/2||Ax - b||^2, the smooth part of the Section 4.2 LASSO).  x_dev: n elements, r_dev: m
+ * elements (16-byte aligned), both of the problem's dtype, caller-owned.  Stream-ordered. */
 sca_status sca_residual(sca_problem* p, const void* x_dev, void* r_dev, void* stream);
 
 /* Fill mask_dev[i] (uint8, nblocks) with 1 when block i is drawn in round k (step S.1).
@@ -176,8 +184,10 @@ sca_status sca_select_blocks(sca_problem* p, const sca_opts* opts, int64_t k, ui
 sca_status sca_philox4x32_10(const uint32_t* in_dev, uint32_t* out_dev, int64_t count,
                              void* stream);
 
-/* Stationarity report at x_dev with a fresh residual (FP64 accumulation):
- * F, ||xh(x)-x||_inf, ||M_F(x)||_2 and nnz(xh(x)); any output pointer may be NULL.
+/* Stationarity report at x_dev (n elements) with a fresh residual (FP64 accumulation):
+ * F = 1/2||Ax-b||^2 - c||x||^2 + lam sum h(x_j) (the objective whose relative error
+ * Section 4.2 measures), the merit ||xh(x)-x||_inf of Section 4.3, ||M_F(x)||_2 (the
+ * unit-step proximal residual of Section 3) and nnz(xh(x)); any output pointer may be NULL.
  * opts supplies tau.  Synchronises 'stream'. */
 sca_status sca_objective(sca_problem* p, const sca_opts* opts, const void* x_dev, double* F,
                          double* merit, double* MF, int64_t* nnz, void* stream);

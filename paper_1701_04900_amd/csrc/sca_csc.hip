@@ -803,8 +803,11 @@ k_bin_scatter(const long long* __restrict__ colptr, const int* __restrict__ rowi
 // truncated toward zero) and split into 32-bit chunks, each added to its limb with a
 // non-returning LDS atomic; a limb takes 2^31 such additions before it can overflow.
 // Integer sums do not depend on the order of the additions; carries are resolved once
-// when the cell is read.  Magnitudes up to 2^55 per row are represented.
+// when the cell is read.  Magnitudes below 2^55 are represented, per entry and per row sum:
+// an entry outside that range (or Inf / NaN) is not added but reported to the caller, and a
+// row sum beyond it reads as NaN, so an out-of-range fold shows up as a non-finite residual.
 constexpr int kLimbs = 4;
+constexpr double kLimbRange = 36028797018963968.0;  // 2^55
 __device__ __forceinline__ void limb_add(long long* cell, int R, unsigned long long M, int s,
                                          bool neg) {
   if (s < 0) {
@@ -815,36 +818,37 @@ __device__ __forceinline__ void limb_add(long long* cell, int R, unsigned long l
   if (M == 0ull) return;
   int k = s >> 5;
   const int o = s & 31;
-  // M < 2^53 and o < 32: M << o spans at most three 32-bit chunks
+  // M < 2^53 and o < 32: M << o spans at most three 32-bit chunks; below 2^55 the top
+  // set bit is at most bit 126, so no chunk lies beyond the top limb
   const unsigned long long lo = M << o;
   const unsigned long long hi = o ? (M >> (64 - o)) : 0ull;
   const unsigned long long ch[3] = {lo & 0xffffffffull, lo >> 32, hi};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    if (ch[i] == 0ull) continue;
-    long long c = (long long)ch[i];
-    int kk = k + i;
-    if (kk >= kLimbs) {  // beyond the represented range: fold into the top limb (or drop)
-      if (kk > kLimbs) continue;
-      c <<= 32;
-      kk = kLimbs - 1;
-    }
-    atomicAdd((unsigned long long*)&cell[kk * R], (unsigned long long)(neg ? -c : c));
+    const int kk = k + i;
+    if (ch[i] == 0ull || kk >= kLimbs) continue;
+    const unsigned long long c = ch[i];
+    atomicAdd((unsigned long long*)&cell[kk * R], neg ? 0ull - c : c);
   }
 }
-__device__ __forceinline__ void limb_add_val(long long* cell, int R, float v) {
+// Adds v to the cell; returns false (adding nothing) when |v| >= 2^55 or v is not finite.
+__device__ __forceinline__ bool limb_add_val(long long* cell, int R, float v) {
+  if (!(fabsf(v) < (float)kLimbRange)) return false;
   const uint32_t u = __float_as_uint(v);
   const int ex = (int)((u >> 23) & 0xffu);
-  if (ex == 0) return;  // zero or subnormal: below the unit
+  if (ex == 0) return true;  // zero or subnormal: below the unit
   const unsigned long long M = (unsigned long long)((u & 0x7fffffu) | 0x800000u);
   limb_add(cell, R, M, ex - 127 - 23 + 72, (u >> 31) != 0u);
+  return true;
 }
-__device__ __forceinline__ void limb_add_val(long long* cell, int R, double v) {
+__device__ __forceinline__ bool limb_add_val(long long* cell, int R, double v) {
+  if (!(fabs(v) < kLimbRange)) return false;
   const unsigned long long u = (unsigned long long)__double_as_longlong(v);
   const int ex = (int)((u >> 52) & 0x7ffull);
-  if (ex == 0) return;
+  if (ex == 0) return true;
   const unsigned long long M = (u & 0xfffffffffffffull) | (1ull << 52);
   limb_add(cell, R, M, ex - 1023 - 52 + 72, (u >> 63) != 0ull);
+  return true;
 }
 // Value of a cell in one rounding from its 128-bit two's-complement integer.
 __device__ __forceinline__ double limb_value(const long long* cell, int R) {
@@ -855,6 +859,8 @@ __device__ __forceinline__ double limb_value(const long long* cell, int R) {
   t = cell[2 * R] + (t >> 32);
   const unsigned long long c2 = (unsigned long long)t & 0xffffffffull;
   t = cell[3 * R] + (t >> 32);
+  // the 128-bit sum is t * 2^96 + (c2, c1, c0): beyond 2^55 (t outside 32 bits) it wrapped
+  if (t < -2147483648ll || t > 2147483647ll) return __longlong_as_double(0x7ff8000000000000ll);
   const long long hi = (long long)(((unsigned long long)t << 32) | c2);
   const unsigned long long lo = (c1 << 32) | c0;
   return ldexp((double)hi, 64 - 72) + ldexp((double)lo, -72);
@@ -862,7 +868,9 @@ __device__ __forceinline__ double limb_value(const long long* cell, int R) {
 
 // One workgroup per bin: the bin's entries are summed into limb cells in LDS (eight entry
 // loads per thread in flight), then out[i] = base_scale * base[i] + cell_i for the bin's
-// rows (one rounding; out may alias base; out and out64 may each be NULL).
+// rows (one rounding; out may alias base; out and out64 may each be NULL).  A row that
+// received an entry the cells cannot hold (see limb_add_val) is written as NaN.
+// Dynamic LDS: kLimbs * R long longs of cells, then R ints of flags.
 constexpr int kAccThreads = 1024;
 constexpr int kAccUnroll = 8;
 template <typename T, typename TB, typename TO>
@@ -873,7 +881,9 @@ k_bin_acc(const Ent<T>* __restrict__ ent, const int* __restrict__ tot, int bin_l
   __shared__ long long s_part[kAccThreads / 64];
   const int R = 1 << bin_log;
   const int bin = blockIdx.x;
+  int* bad = (int*)(cells + kLimbs * R);
   for (int i = threadIdx.x; i < kLimbs * R; i += kAccThreads) cells[i] = 0;
+  for (int i = threadIdx.x; i < R; i += kAccThreads) bad[i] = 0;
   long long pre = 0;
   for (int i = threadIdx.x; i < bin; i += kAccThreads) pre += tot[i];
   pre = wave_sum_i64(pre);
@@ -892,14 +902,16 @@ k_bin_acc(const Ent<T>* __restrict__ ent, const int* __restrict__ tot, int bin_l
 #pragma unroll
     for (int u = 0; u < kAccUnroll; ++u) {
       const bool ok = e0 + (long long)u * kAccThreads < end;
-      limb_add_val(&cells[ok ? (int)en[u].row : 0], R, ok ? en[u].val : (T)0);
+      const int row = ok ? (int)en[u].row : 0;
+      if (!limb_add_val(&cells[row], R, ok ? en[u].val : (T)0)) atomicOr(&bad[row], 1);
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < R; i += kAccThreads) {
     const int row = bin * R + i;
     if (row >= m) break;
-    const double s = base_scale * (double)base[row] + limb_value(&cells[i], R);
+    const double s = bad[i] ? __longlong_as_double(0x7ff8000000000000ll)
+                            : base_scale * (double)base[row] + limb_value(&cells[i], R);
     if (out) out[row] = (TO)s;
     if (out64) out64[row] = s;
   }
@@ -970,7 +982,7 @@ void bin_fold(sca_problem* p, const int* list, const int* count_ptr, int count, 
                        (const T*)p->csc_vals, list, count_ptr, count, coef, p->bin_log, nb,
                        (const int*)p->d_bin_cnt, (const int*)p->d_bin_tot, (Ent<T>*)p->d_ent);
   hipLaunchKernelGGL((k_bin_acc<T, TB, TO>), dim3(nb), dim3(kAccThreads),
-                     sizeof(long long) * kLimbs * ((size_t)1 << p->bin_log), s,
+                     (sizeof(long long) * kLimbs + sizeof(int)) * ((size_t)1 << p->bin_log), s,
                      (const Ent<T>*)p->d_ent, (const int*)p->d_bin_tot, p->bin_log, (int)p->m,
                      base, base_scale, out, out64);
 }

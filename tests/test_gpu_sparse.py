@@ -166,3 +166,40 @@ def test_sparse_rejects_bad_csr():
     with pytest.raises(sca.SCAError) as e:
         sca.Problem.csr(w.m, w.n, rp, w.colidx, w.vals, w.b, w.lam, block_ptr=w.block_ptr)
     assert e.value.status == sca.SCA_EINVAL
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_sparse_fold_out_of_range_products_become_nan(dtype):
+    """The exact fixed-point fold holds products and row sums below 2^55: with b and lam
+    scaled by 1e18 (the solution scales with them) the first round's moves give products
+    beyond that, and the rows they reach turn into NaN -- never a silently wrong finite
+    residual -- while rows no moved column reaches keep r = -b; a solve stops with
+    SCA_ENONFINITE."""
+    w = inputs.sparse_problem(600, 3000, per_col=6, nnz_frac=0.01, lam_frac=0.01, block=32,
+                              p=1.0, dtype=dtype, seed=9)
+    w.b = w.b * 1e18
+    w.lam = w.lam * 1e18
+    prob = _oracle(w)
+    run = Run(w)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(run.r).all())  # r = -b: nothing folded yet
+    run.step(1)
+    r = run.r.double().cpu().numpy()
+    # the oracle's first round (FP64 holds these magnitudes): which columns move
+    x1, _, _ = O.run_rounds(prob, O.RunConfig(tau=w.tau, gamma=w.gamma, p=1.0, seed=w.seed),
+                            np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0, 1)
+    csc = w.scipy_csr().tocsc()
+    reach = np.zeros(w.m, dtype=bool)
+    for j in np.flatnonzero(x1):
+        reach[csc[:, j].indices] = True
+    assert np.isnan(r).any()
+    assert not np.isnan(r[~reach]).any()
+    b = w.b.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(r[~reach], -b[~reach])
+    # a solve from x = 0 reports the non-finite objective
+    o = sca.make_opts(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed, max_rounds=20,
+                      check_every=5)
+    x = torch.zeros(w.n, dtype=dtype, device="cuda")
+    with pytest.raises(sca.SCAError) as e:
+        sca.sca_solve(run.P.handle, o, x)
+    assert e.value.status == sca.SCA_ENONFINITE
