@@ -10,6 +10,7 @@ import torch
 
 from oracle import sca_oracle as O
 from paper_1701_04900_amd import inputs, sca
+from fp32_tolerance import x_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -103,7 +104,9 @@ def test_batch_fp32_objective_up_to_8192_rows():
         prob, xo, _, _, _ = _oracle_rounds(w, k, 0.25, 7, 20)
         Fo = O.objective(prob, xo)
         assert abs(rep["F"][k] - Fo) <= 1e-4 * abs(Fo), k
-        assert _rel(x[B.xoff[k]:B.xoff[k + 1]].double().cpu().numpy(), xo) <= 1e-3, k
+        ex = _rel(x[B.xoff[k]:B.xoff[k + 1]].double().cpu().numpy(), xo)
+        print(f"[parity] batch fp32 instance {k} m={w.m}: x err {ex:.2e}", flush=True)
+        assert ex <= x_tol(w.m), k
 
 
 def test_batch_with_a_4097_row_instance_fp64():

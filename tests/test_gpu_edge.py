@@ -19,6 +19,7 @@ import torch
 
 from oracle import sca_oracle as O
 from paper_1701_04900_amd import inputs, sca
+from fp32_tolerance import x_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -184,7 +185,8 @@ def test_padding_rows_of_A_never_reach_a_result(kind, dtype):
     xg, rg = run.step(10)
     assert np.all(np.isfinite(xg)) and np.all(np.isfinite(rg))
     xo, ro, _ = _oracle_rounds(w, prob, 10)
-    tol = 1e-10 if dtype == torch.float64 else 1e-3
+    tol = 1e-10 if dtype == torch.float64 else x_tol(w.m)
+    print(f"[parity] padding rows {kind} {dtype}: x err {_rel(xg, xo):.2e}, r err {_rel(rg, ro):.2e}", flush=True)
     assert _rel(xg, xo) <= tol and _rel(rg, ro) <= tol
     rep = sca.sca_objective(run.P.handle, run.opts, run.x)
     assert math.isfinite(rep["F"]) and math.isfinite(rep["merit"])

@@ -1,9 +1,13 @@
 """Parity at the full configuration sizes, in the launch configuration the benchmark uses
 (the installed tuning table).  The oracle runs the first rounds on the host copy of the
-same data; FP32 tolerances: objective 1e-4 relative, iterates 1e-3 of max(1, ||x||_inf).
+same data (20 rounds of the dense workloads, 10 of the sparse one and of the sampled batch
+instances and right-hand sides), compared after every round.
+
+FP32 tolerances: the objective within 1e-4 relative (the stated FP32 target), the iterates
+within x_tol(terms) of max(1, ||x||_inf), terms = the products of one partial gradient (m
+dense, the column's nonzeros sparse); x_tol is derived in fp32_tolerance.py.
 Round 1 is also checked one coordinate at a time: from x^0 = 0, x^1_j = gamma *
 clip(soft(a_j^T b / q_j, lam / q_j)) for the drawn j and 0 elsewhere."""
-import math
 
 import numpy as np
 import pytest
@@ -11,14 +15,37 @@ import torch
 
 from oracle import sca_oracle as O
 from paper_1701_04900_amd import inputs, sca
+from fp32_tolerance import x_tol
 
-pytestmark = pytest.mark.gpu
+# the oracle's FP64 rounds over 2-8 GB of A take seconds each on the host
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 
 
 def _rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b)))))
+
+
+def _compare_rounds(name, w, prob, gpu, cfg, rounds, terms=None):
+    """Run the oracle for the same rounds and compare every round; print all errors first
+    (so a failure shows the whole trajectory), then assert."""
+    x = np.zeros(w.n)
+    r = O.residual(prob, x)
+    ex, eF = [], []
+    for k in range(rounds):
+        x, r, _ = O.run_rounds(prob, cfg, x, r, k, 1)
+        Fo = O.objective(prob, x, r)
+        ex.append(_rel(gpu[k][0], x))
+        eF.append(abs(gpu[k][1] - Fo) / abs(Fo))
+        print(f"[parity] {name} round {k + 1}: x err {ex[-1]:.2e}, F rel err {eF[-1]:.2e}",
+              flush=True)
+    tol = x_tol(w.m if terms is None else terms)
+    print(f"[parity] {name}: max x err {max(ex):.2e} (tolerance {tol:.2e}), max F rel err "
+          f"{max(eF):.2e} (tolerance 1e-4)", flush=True)
+    assert max(ex) <= tol
+    assert max(eF) <= 1e-4
+    return x
 
 
 def _gpu_rounds(w, P, rounds):
@@ -57,22 +84,13 @@ def test_lasso_20000x100000_fp32_full_size():
     print("[gpu] full-size dense LASSO 20000x100000 FP32", flush=True)
     w = inputs.lasso_dense_fp32(device="cuda")
     P = sca.Problem.from_workload(w)
-    gpu, _, _ = _gpu_rounds(w, P, 2)
+    gpu, _, _ = _gpu_rounds(w, P, 20)
     At = w.At.cpu()
     prob = O.Problem(A=At[:, : w.m].numpy().T, b=w.b.double().cpu().numpy(), lam=w.lam,
                      block_ptr=w.block_ptr)
     _first_round_one_by_one(w, prob, gpu[0][0])
     cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
-    x = np.zeros(w.n)
-    r = O.residual(prob, x)
-    for k in range(2):
-        x, r, _ = O.run_rounds(prob, cfg, x, r, k, 1)
-        assert _rel(gpu[k][0], x) <= 1e-3
-        Fo = O.objective(prob, x, r)
-        Fg = gpu[k][1]
-        assert abs(Fg - Fo) <= 1e-4 * abs(Fo), (k, Fg, Fo)
-        print(f"[parity] full-size LASSO round {k + 1}: x err {_rel(gpu[k][0], x):.2e}, "
-              f"F rel err {abs(Fg - Fo) / abs(Fo):.2e}", flush=True)
+    _compare_rounds("full-size LASSO", w, prob, gpu, cfg, 20)
     P.close()
 
 
@@ -80,18 +98,12 @@ def test_nonconvex_box_10000x50000_fp32_full_size():
     print("[gpu] full-size box-nonconvex 10000x50000 FP32", flush=True)
     w = inputs.nonconvex_box_fp32(device="cuda")
     P = sca.Problem.from_workload(w)
-    gpu, _, _ = _gpu_rounds(w, P, 3)
+    gpu, _, _ = _gpu_rounds(w, P, 20)
     At = w.At.cpu()
     prob = O.Problem(A=At[:, : w.m].numpy().T, b=w.b.double().cpu().numpy(), lam=w.lam, c=w.c,
                      beta=w.beta, block_ptr=w.block_ptr)
     cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
-    x = np.zeros(w.n)
-    r = O.residual(prob, x)
-    for k in range(3):
-        x, r, _ = O.run_rounds(prob, cfg, x, r, k, 1)
-        assert _rel(gpu[k][0], x) <= 1e-3
-        Fo = O.objective(prob, x, r)
-        assert abs(gpu[k][1] - Fo) <= 1e-4 * abs(Fo)
+    _compare_rounds("full-size box-nonconvex", w, prob, gpu, cfg, 20)
     assert np.max(np.abs(gpu[-1][0])) <= 1.0
     P.close()
 
@@ -100,18 +112,12 @@ def test_sparse_lasso_100000x1000000_fp32_full_size():
     print("[gpu] full-size sparse LASSO 1e5 x 1e6, 1e8 nonzeros, FP32", flush=True)
     w = inputs.sparse_lasso_fp32(device="cuda")
     P = sca.Problem.from_workload(w)
-    gpu, _, _ = _gpu_rounds(w, P, 2)
+    gpu, _, _ = _gpu_rounds(w, P, 10)
     prob = O.Problem(A=w.scipy_csr().tocsc(), b=w.b.double().cpu().numpy(), lam=w.lam,
                      block_ptr=w.block_ptr)
     _first_round_one_by_one(w, prob, gpu[0][0], nsample=500)
     cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
-    x = np.zeros(w.n)
-    r = O.residual(prob, x)
-    for k in range(2):
-        x, r, _ = O.run_rounds(prob, cfg, x, r, k, 1)
-        assert _rel(gpu[k][0], x) <= 1e-3
-        Fo = O.objective(prob, x, r)
-        assert abs(gpu[k][1] - Fo) <= 1e-4 * abs(Fo)
+    _compare_rounds("full-size sparse LASSO", w, prob, gpu, cfg, 10, terms=w.nnz // w.n)
     P.close()
 
 
@@ -124,19 +130,19 @@ def test_batch_256_full_size_sampled_instances():
     x = torch.zeros(int(B.xoff[-1]), dtype=torch.float32, device="cuda")
     r = torch.zeros(int(B.roff[-1]), dtype=torch.float32, device="cuda")
     sca.sca_batch_residual(B.handle, x, r)
-    sca.sca_batch_step(B.handle, o, 0, 2, x, r)
-    Fg_all = sca.sca_batch_objective(B.handle, o, x, B.K)["F"]
-    xh = x.double().cpu().numpy()
+    rounds = 10
+    per_round = []
+    for k in range(rounds):
+        sca.sca_batch_step(B.handle, o, k, 1, x, r)
+        Fg_all = sca.sca_batch_objective(B.handle, o, x, B.K)["F"]
+        per_round.append((x.double().cpu().numpy(), Fg_all))
     for k in (0, 97, 255):  # smallest lam, a middle one, largest lam
         w = ws[k]
         prob = O.Problem(A=w.At[:, : w.m].cpu().numpy().T, b=w.b.double().cpu().numpy(),
                          lam=w.lam, block_ptr=w.block_ptr)
         cfg = O.RunConfig(tau=w.tau, gamma=0.9, p=0.25, seed=0, instance=k)
-        xo, ro, _ = O.run_rounds(prob, cfg, np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0, 2)
-        xg = xh[B.xoff[k]:B.xoff[k + 1]]
-        assert _rel(xg, xo) <= 1e-3, k
-        Fo = O.objective(prob, xo, ro)
-        assert abs(Fg_all[k] - Fo) <= 1e-4 * abs(Fo), k
+        gpu = [(xa[B.xoff[k]:B.xoff[k + 1]], Fa[k]) for xa, Fa in per_round]
+        _compare_rounds(f"full-size batch instance {k} (m={w.m})", w, prob, gpu, cfg, rounds)
     B.close()
 
 
@@ -151,11 +157,12 @@ def test_multi_rhs_20000x100000_K64_fp32_full_size():
     X = M.zeros_x()
     R = M.empty_r()
     sca.sca_multi_residual(M.handle, X, R)
-    sca.sca_multi_step(M.handle, o, 0, 1, X, R)
-    X1 = X.double().cpu().numpy()
-    sca.sca_multi_step(M.handle, o, 1, 1, X, R)
-    F2 = sca.sca_multi_objective(M.handle, o, X, w.K)["F"]
-    X2 = X.double().cpu().numpy()
+    rounds = 5
+    per_round = []
+    for k in range(rounds):
+        sca.sca_multi_step(M.handle, o, k, 1, X, R)
+        per_round.append((X.double().cpu().numpy(), sca.sca_multi_objective(M.handle, o, X, w.K)["F"]))
+    X1 = per_round[0][0]
     A32 = w.At.cpu()[:, : w.m].numpy().T
     for k in (0, 32, 63):
         wk = inputs.DenseWorkload(w.name, w.At, w.m, w.n, w.lda, w.B[k, : w.m], w.base.x_true,
@@ -165,10 +172,6 @@ def test_multi_rhs_20000x100000_K64_fp32_full_size():
                          block_ptr=w.block_ptr)
         _first_round_one_by_one(wk, prob, X1[k], nsample=1000)
         cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
-        x, r, _ = O.run_rounds(prob, cfg, np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0, 2)
-        assert _rel(X2[k], x) <= 1e-3, k
-        Fo = O.objective(prob, x, r)
-        assert abs(F2[k] - Fo) <= 1e-4 * abs(Fo), (k, F2[k], Fo)
-        print(f"[parity] multi full-size problem {k}: x err {_rel(X2[k], x):.2e}, "
-              f"F rel err {abs(F2[k] - Fo) / abs(Fo):.2e}", flush=True)
+        gpu = [(Xa[k], Fa[k]) for Xa, Fa in per_round]
+        _compare_rounds(f"multi full-size problem {k}", wk, prob, gpu, cfg, rounds)
     M.close()

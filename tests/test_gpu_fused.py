@@ -16,6 +16,7 @@ import torch
 
 from oracle import sca_oracle as O
 from paper_1701_04900_amd import inputs, sca
+from fp32_tolerance import x_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -184,7 +185,8 @@ def test_fused_fp32_objective(m, n, cols):
         Fo = O.objective(prob, xo)
         Fg = sca.sca_objective(run.P.handle, run.opts, run.x)["F"]
         assert abs(Fg - Fo) <= 1e-4 * abs(Fo), (run.k, Fg, Fo)
-        assert _rel(xg, xo) <= 1e-3
+        print(f"[parity] fused fp32 {m}x{n} round {run.k}: x err {_rel(xg, xo):.2e}", flush=True)
+        assert _rel(xg, xo) <= x_tol(m), (run.k, _rel(xg, xo))
 
 
 @pytest.mark.parametrize("dtype,m", [(torch.float64, 3001), (torch.float32, 9001)])

@@ -10,6 +10,7 @@ import torch
 
 from oracle import sca_oracle as O
 from paper_1701_04900_amd import inputs, sca
+from fp32_tolerance import x_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -102,7 +103,8 @@ def test_multi_fp32_objectives():
                                30)
         Fo = O.objective(prob, x, r)
         assert abs(rep["F"][k] - Fo) <= 1e-4 * abs(Fo), k
-        assert _rel(X[k].double().cpu().numpy(), x) <= 1e-3, k
+        print(f"[parity] multi fp32 m={w.m} problem {k}: x err {_rel(X[k].double().cpu().numpy(), x):.2e}", flush=True)
+        assert _rel(X[k].double().cpu().numpy(), x) <= x_tol(w.m), k
     M.close()
 
 
@@ -209,5 +211,6 @@ def test_multi_fp32_ragged_rows_with_nan_padding():
                                20)
         Fo = O.objective(prob, x, r)
         assert abs(rep["F"][k] - Fo) <= 1e-4 * abs(Fo), k
-        assert _rel(X[k].double().cpu().numpy(), x) <= 1e-3, k
+        print(f"[parity] multi fp32 m={w.m} problem {k}: x err {_rel(X[k].double().cpu().numpy(), x):.2e}", flush=True)
+        assert _rel(X[k].double().cpu().numpy(), x) <= x_tol(w.m), k
     M.close()

@@ -18,6 +18,7 @@ import torch
 
 from oracle import sca_oracle as O
 from paper_1701_04900_amd import inputs, sca
+from fp32_tolerance import x_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -88,7 +89,8 @@ def test_sparse_gradient_paths_fp32_objective(m, n, per_col, block, p):
     Fo = O.objective(prob, xo)
     Fg = sca.sca_objective(P.handle, o, x)["F"]
     assert abs(Fg - Fo) <= 1e-4 * abs(Fo)
-    assert _rel(gpu[-1][0], xo) <= 1e-3
+    print(f"[parity] sparse fp32 m={w.m}: x err {_rel(gpu[-1][0], xo):.2e}", flush=True)
+    assert _rel(gpu[-1][0], xo) <= x_tol(w.nnz // w.n), _rel(gpu[-1][0], xo)
     P.close()
 
 
@@ -101,7 +103,8 @@ def test_sparse_split_fp32_three_panels_objective():
     Fo = O.objective(prob, xo)
     Fg = sca.sca_objective(P.handle, o, x)["F"]
     assert abs(Fg - Fo) <= 1e-4 * abs(Fo)
-    assert _rel(gpu[-1][0], xo) <= 1e-3
+    print(f"[parity] sparse fp32 m={w.m}: x err {_rel(gpu[-1][0], xo):.2e}", flush=True)
+    assert _rel(gpu[-1][0], xo) <= x_tol(w.nnz // w.n), _rel(gpu[-1][0], xo)
     P.close()
 
 
