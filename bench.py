@@ -39,18 +39,82 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def reference_optimum(w, opts_kw):
+F_STAR_MERIT = 1e-13
+F_STAR_GAP = 1e-10     # the gap that certifies F* (reported as "certified")
+F_STAR_GAP_FAIL = 1e-8  # a gap beyond this (1% of the 1e-6 tolerance) stops the bench
+
+
+def _checked_fstar_solve(st, what):
+    """The F* solve must have converged: a solve stopped short would overstate F* and end
+    the timed solves early."""
+    if st["status"] != sca.SCA_OK or not st["merit"] <= F_STAR_MERIT:
+        raise RuntimeError(f"{what}: the FP64 reference solve did not reach merit "
+                           f"{F_STAR_MERIT:g} (status {st['status']}, merit {st['merit']:.3e}, "
+                           f"{st['rounds']} rounds)")
+
+
+def reference_optimum(w, opts_kw, want_x=False):
     """F* by an FP64 solve of the stored FP32 data (upcast copy) to merit <= 1e-12."""
     At64 = w.At.double()
     b64 = w.b.double()
     P = sca.Problem.dense(At64, w.m, b64, w.lam, w.c, w.beta, w.block_ptr)
-    o = sca.make_opts(**opts_kw, max_rounds=200000, check_every=50, tol_merit=1e-12)
+    o = sca.make_opts(**opts_kw, max_rounds=200000, check_every=50, tol_merit=F_STAR_MERIT)
     x = torch.zeros(w.n, dtype=torch.float64, device="cuda")
     st = sca.sca_solve(P.handle, o, x, raise_on_notconv=False)
     P.close()
     del At64, b64
     torch.cuda.empty_cache()
+    _checked_fstar_solve(st, w.name)
+    if want_x:
+        return st["F"], st, x.cpu().numpy()
     return st["F"], st
+
+
+def certify_fstar(w, F_star, xstar):
+    """An FP64 check of F* on the host that shares nothing with the GPU path: at the FP64
+    solution x* (l1 regulariser, no box, c = 0) it recomputes with numpy (scipy for sparse A)
+    the residual r = A x* - b, the objective P(x*) = 1/2||r||^2 + lam ||x*||_1, the gradient
+    g = A^T r over all columns, ||M_F(x*)||_2 = ||x* - soft(x* - g, lam)||_2 and the LASSO
+    duality gap: nu = s r with s = min(1, lam / ||g||_inf) is dual feasible, its dual value is
+    D = -1/2||nu||^2 - b^T nu <= P*, so P(x*) - D bounds the error of F* = P(x*).  F* is
+    accepted when the gap is <= 1e-10 |F*|."""
+    t0 = time.perf_counter()
+    xs = np.asarray(xstar, dtype=np.float64)
+    b = w.b.double().cpu().numpy()
+    nz = np.flatnonzero(xs)
+    if hasattr(w, "rowptr"):
+        A = w.scipy_csr().astype(np.float64)
+        r = A @ xs - b
+        g = np.asarray(A.T @ r).ravel()
+    else:
+        At = w.At.cpu()  # (n, lda) FP32, row j = column j of A
+        r = -b.copy()
+        for j0 in range(0, len(nz), 4096):
+            idx = torch.from_numpy(nz[j0:j0 + 4096])
+            cols = At[idx, : w.m].double().numpy()
+            r += cols.T @ xs[nz[j0:j0 + 4096]]
+        g = np.empty(w.n)
+        for j0 in range(0, w.n, 8192):
+            g[j0:j0 + 8192] = At[j0:j0 + 8192, : w.m].double().numpy() @ r
+    P = 0.5 * float(r @ r) + w.lam * float(np.abs(xs).sum())
+    v = xs - g
+    y = np.sign(v) * np.maximum(np.abs(v) - w.lam, 0.0)
+    MF = float(np.linalg.norm(xs - y))
+    s = min(1.0, w.lam / float(np.max(np.abs(g))))
+    D = -0.5 * s * s * float(r @ r) - s * float(b @ r)
+    gap = P - D
+    out = dict(F_star=F_star, host_F=P, host_MF=MF, dual=D, gap=gap,
+               rel_gap=gap / abs(P), F_star_vs_host=abs(F_star - P) / abs(P),
+               certified=bool(gap <= F_STAR_GAP * abs(P)
+                              and abs(F_star - P) <= F_STAR_GAP * abs(P)),
+               seconds=round(time.perf_counter() - t0, 2),
+               method="numpy FP64 on the host at the FP64 GPU solution: fresh residual, "
+                      "objective, ||M_F||, LASSO duality gap")
+    log(f"F* check ({w.name}): host F {P:.15g}, gap {gap:.3e} ({gap / abs(P):.2e} relative), "
+        f"||M_F|| {MF:.2e}, {out['seconds']} s")
+    if not (gap <= F_STAR_GAP_FAIL * abs(P) and abs(F_star - P) <= F_STAR_GAP_FAIL * abs(P)):
+        raise RuntimeError(f"F* of {w.name} is not within {F_STAR_GAP_FAIL:g} of the optimum: {out}")
+    return out
 
 
 def cpu_baseline(w, opts_kw, rounds):
@@ -477,10 +541,13 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
     fetch_b = res["FETCH_SIZE"]["grad_kib_mean"] * 1024 * res["FETCH_SIZE"]["scale"]
     write_b = res["WRITE_SIZE"]["grad_kib_mean"] * 1024 * res["WRITE_SIZE"]["scale"]
     drawn = probe["coord_updates"] / probe["rounds"]
+    impl_b = 0.0
     if kind == "sparse":
         alg_b = drawn * probe["per_col"] * (4 + 4)
     else:
         alg_b = round_alg_bytes(probe["launch"], drawn, probe["m"], 4, probe.get("groups", 0))
+        if probe["launch"]["grad_kind"] == 4:
+            impl_b = probe.get("groups", 0) * probe["m"] * 4
     fp = kernel_fingerprint(probe["launch"], kind)
     lines = [
         title,
@@ -507,13 +574,21 @@ def pmc_summarize(fetch_dir, write_dir, probe_json):
         f"algorithmic_bytes_per_launch: {alg_b:.0f}",
         f"traffic_over_algorithmic: {(fetch_b + write_b) / alg_b:.4f}",
     ]
+    if impl_b:
+        lines += [
+            f"fold_partial_bytes_per_launch: {impl_b:.0f}",
+            f"traffic_over_algorithmic_and_partials: {(fetch_b + write_b) / (alg_b + impl_b):.4f}",
+            "(algorithmic bytes: the drawn columns, m x 4 B each, read once -- the method's "
+            "reads; the fused round also writes one m-vector of fold partials per workgroup, "
+            "counted on the line above)"]
     open(PMC_SUMMARY[kind], "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
 def pmc_traffic(launch, kind="lasso"):
-    """Traffic per launch from the committed counter summary, or None when it is absent or
-    was taken on other kernel code or another launch shape."""
+    """Traffic per launch from the committed counter summary and the algorithmic bytes of
+    the probe rounds it was read over (dict), or None when it is absent or was taken on
+    other kernel code or another launch shape."""
     if not os.path.exists(PMC_SUMMARY[kind]):
         return None
     kv = {}
@@ -523,7 +598,8 @@ def pmc_traffic(launch, kind="lasso"):
             kv[k.strip()] = v.strip()
     if kv.get("fingerprint") != kernel_fingerprint(launch, kind):
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return dict(traffic=float(kv["traffic_bytes_per_launch"]),
+                alg=float(kv["algorithmic_bytes_per_launch"]))
 
 
 def main():
@@ -539,9 +615,12 @@ def main():
                          "100 box-nonconvex, 100 sparse)")
     ap.add_argument("--rounds", type=int, default=3000,
                     help="rounds per step of the box-nonconvex workload")
-    ap.add_argument("--seeds", type=int, default=1,
-                    help="data seeds 0..S-1 of lasso/nonconvex/sparse, each with K timed solves; "
-                         "S > 1 reports the medians over seeds")
+    ap.add_argument("--seeds", type=int, default=5,
+                    help="data seeds 0..S-1 of the headline workload, each with K timed solves; "
+                         "S > 1 reports the medians over seeds (the paper averages 5 "
+                         "realisations)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: skip the sparse, box-nonconvex and 200x1000 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", choices=["lasso", "nonconvex", "sparse", "batch", "multi",
@@ -579,8 +658,13 @@ def main():
     if args.pmc_probe:
         pmc_probe(args)
         return
-
-    bench_single(args)
+    if args.workload == "lasso":
+        bench_default(args)
+        return
+    cr = None if args.no_cpu_baseline else (args.cpu_rounds or 100)
+    out = run_single(args.workload, args, args.steps, args.warmup, seeds=1,
+                     profile=not args.no_profile, cpu_rounds=cr)
+    print(json.dumps(out), flush=True)
 
 
 def make_workload(kind, args, seed=0):
@@ -591,11 +675,12 @@ def make_workload(kind, args, seed=0):
     return inputs.sparse_lasso_fp32(seed=seed, device="cuda")
 
 
-def extra_seeds(kind, args, opts_base):
+def extra_seeds(kind, args, opts_base, seeds, steps, warmup):
     """Data seeds 1 .. S-1 of the same workload (seed 0 is timed by the caller): per seed a
-    fresh workload, its own F*, warm-up and K timed solves.  Returns per-seed results."""
+    fresh workload, its own F* (an FP64 solve that must reach merit 1e-13), warm-up and K
+    timed solves.  Returns per-seed results."""
     out = []
-    for seed in range(1, args.seeds):
+    for seed in range(1, seeds):
         w = make_workload(kind, args, seed)
         okw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
         stop_kw, max_rounds, notconv_ok = opts_base
@@ -606,20 +691,20 @@ def extra_seeds(kind, args, opts_base):
         P = sca.Problem.from_workload(w)
         opts = sca.make_opts(**okw, max_rounds=max_rounds, check_every=10, **stop_kw)
         x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             x.zero_()
             sca.sca_solve(P.handle, opts, x, raise_on_notconv=not notconv_ok)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
-        for _ in range(args.steps):
+        for _ in range(steps):
             x.zero_()
             stats.append(sca.sca_solve(P.handle, opts, x, raise_on_notconv=not notconv_ok))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        res = dict(seed=seed, ms_per_step=el / args.steps * 1e3,
+        res = dict(seed=seed, ms_per_step=el / steps * 1e3,
                    value=sum(s["coord_updates"] for s in stats) / el,
-                   rounds_per_solve=sum(s["rounds"] for s in stats) / args.steps,
+                   rounds_per_solve=sum(s["rounds"] for s in stats) / steps,
                    rel_err_final=stats[-1]["rel_err"], merit_final=stats[-1]["merit"])
         log(f"seed {seed}: {res}")
         out.append(res)
@@ -629,15 +714,18 @@ def extra_seeds(kind, args, opts_base):
     return out
 
 
-def sparse_reference_optimum(w, opts_kw):
+def sparse_reference_optimum(w, opts_kw, want_x=False):
     """F* by an FP64 solve of the stored FP32 CSR data (upcast copy) to merit <= 1e-12."""
     P = sca.Problem.csr(w.m, w.n, w.rowptr, w.colidx, w.vals.double(), w.b.double(), w.lam,
                         w.c, w.beta, w.block_ptr)
-    o = sca.make_opts(**opts_kw, max_rounds=200000, check_every=50, tol_merit=1e-12)
+    o = sca.make_opts(**opts_kw, max_rounds=200000, check_every=50, tol_merit=F_STAR_MERIT)
     x = torch.zeros(w.n, dtype=torch.float64, device="cuda")
     st = sca.sca_solve(P.handle, o, x, raise_on_notconv=False)
     P.close()
     torch.cuda.empty_cache()
+    _checked_fstar_solve(st, w.name)
+    if want_x:
+        return st["F"], st, x.cpu().numpy()
     return st["F"], st
 
 
@@ -653,12 +741,10 @@ def fused_q(m, esize):
 
 
 def round_alg_bytes(L, drawn, m, esize, groups):
-    """Algorithmic bytes of one launch of the gradient kernel: the drawn columns once;
-    the fused kind also writes one m-vector of fold partials per workgroup."""
-    b = drawn * m * esize
-    if L["grad_kind"] == 4:
-        b += groups * m * esize
-    return b
+    """Algorithmic bytes of one launch of the gradient kernel: the drawn columns, once.
+    (The fused kind also writes one m-vector of fold partials per workgroup: traffic of the
+    implementation, not of the method, so not counted here.)"""
+    return drawn * m * esize
 
 
 def grad_kernel_name(L, sparse, m=0):
@@ -693,10 +779,49 @@ def read_stream_peak(buf):
     return best
 
 
-def bench_single(args):
+def cpu_info():
+    """Host cores this process may use and the CPU model (for the CPU baseline rows)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), model
+
+
+def nonconvex_milestones(w, P, opts_kw, rounds, every=50):
+    """Rounds from x = 0 at which the merit ||xhat(x) - x||_inf (Section 4.3) first drops to
+    1e-1, 1e-2, ... (checked every `every` rounds with a fresh FP64 residual), and the merit
+    curve itself; None for a level not reached within `rounds`."""
+    o = sca.make_opts(**opts_kw)
+    x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+    r = torch.empty(w.m, dtype=w.dtype, device="cuda")
+    sca.sca_residual(P.handle, x, r)
+    levels = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+    hit = {lv: None for lv in levels}
+    curve = []
+    k = 0
+    while k < rounds:
+        nr = min(every, rounds - k)
+        sca.sca_step(P.handle, o, k, nr, x, r)
+        k += nr
+        mer = sca.sca_objective(P.handle, o, x)["merit"]
+        curve.append((k, mer))
+        for lv in levels:
+            if hit[lv] is None and mer <= lv:
+                hit[lv] = k
+    return ({f"{lv:g}": hit[lv] for lv in levels},
+            [(k, float(f"{m:.4g}")) for k, m in curve[:: max(1, len(curve) // 20)]] + [curve[-1]])
+
+
+def run_single(kind, args, steps, warmup, seeds=1, profile=True, cpu_rounds=None,
+               certify=True):
     """One problem, K timed solves from x = 0 to tolerance (LASSO: relative objective error
-    against F*; box-nonconvex: merit ||xhat(x) - x||_inf)."""
-    kind = args.workload
+    against F*; box-nonconvex: a fixed budget of rounds, with the merit reached and the
+    rounds to each merit level reported).  Returns the JSON record."""
     sparse = kind == "sparse"
     t0 = time.perf_counter()
     w = make_workload(kind, args)
@@ -712,7 +837,7 @@ def bench_single(args):
     else:
         bytes_per_update = w.m * esize
 
-    F_star = None
+    F_star, fcheck = None, None
     max_rounds = 100000
     notconv_ok = False
     if kind == "nonconvex":
@@ -723,15 +848,20 @@ def bench_single(args):
         notconv_ok = True
     else:
         t0 = time.perf_counter()
-        F_star, st64 = (sparse_reference_optimum if sparse else reference_optimum)(w, opts_kw)
+        F_star, st64, x64 = (sparse_reference_optimum if sparse else reference_optimum)(
+            w, opts_kw, want_x=True)
         log(f"F* = {F_star:.15g} (FP64 solve: {st64['rounds']} rounds, merit "
             f"{st64['merit']:.2e}, {time.perf_counter() - t0:.1f} s)")
+        if certify:
+            fcheck = certify_fstar(w, F_star, x64)
+            fcheck["reference_solve"] = dict(rounds=st64["rounds"], merit=st64["merit"])
+        del x64
         stop_kw = dict(tol_rel_obj=args.tol, F_star=F_star)
 
     P = sca.Problem.from_workload(w)
     opts = sca.make_opts(**opts_kw, max_rounds=max_rounds, check_every=10, **stop_kw)
     x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
-    for i in range(args.warmup):
+    for i in range(warmup):
         x.zero_()
         st = sca.sca_solve(P.handle, opts, x, raise_on_notconv=not notconv_ok)
         log(f"warmup solve {i}: {st['rounds']} rounds, rel err {st['rel_err']:.2e}, "
@@ -740,7 +870,7 @@ def bench_single(args):
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         x.zero_()
         stats.append(sca.sca_solve(P.handle, opts, x, raise_on_notconv=not notconv_ok))
     torch.cuda.synchronize()
@@ -752,15 +882,24 @@ def bench_single(args):
         log(f"solve {i}: {s['rounds']} rounds, {s['coord_updates']} updates, "
             f"{s['seconds'] * 1e3:.1f} ms, rel err {s['rel_err']:.3e}, merit {s['merit']:.2e}")
     per_seed = None
-    if args.seeds > 1:
+    if seeds > 1:
         # the timing protocol over data realisations: seeds 0 .. S-1, medians reported
-        per_seed = [dict(seed=0, ms_per_step=elapsed / args.steps * 1e3, value=value,
-                         rounds_per_solve=rounds / args.steps,
+        per_seed = [dict(seed=0, ms_per_step=elapsed / steps * 1e3, value=value,
+                         rounds_per_solve=rounds / steps,
                          rel_err_final=stats[-1]["rel_err"], merit_final=stats[-1]["merit"])]
-        per_seed += extra_seeds(kind, args, (stop_kw, max_rounds, notconv_ok))
+        per_seed += extra_seeds(kind, args, (stop_kw, max_rounds, notconv_ok), seeds, steps,
+                                warmup)
+
+    milestones = None
+    if kind == "nonconvex":
+        t0 = time.perf_counter()
+        hit, curve = nonconvex_milestones(w, P, opts_kw, max_rounds)
+        milestones = dict(rounds_to_merit=hit, merit_curve=curve,
+                          note="merit from x = 0, checked every 50 rounds (fresh FP64 residual)")
+        log(f"merit milestones in {time.perf_counter() - t0:.1f} s: {hit}")
 
     roof, prof_pass = None, None
-    if not args.no_profile:
+    if profile:
         # the same K solves again with HIP events around every kernel launch (eager launches
         # on the caller's stream: events cannot time kernels inside a replayed graph)
         popts = sca.make_opts(**opts_kw, max_rounds=max_rounds, check_every=10, **stop_kw,
@@ -769,7 +908,7 @@ def bench_single(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pst = []
-        for i in range(args.steps):
+        for i in range(steps):
             x.zero_()
             pst.append(sca.sca_solve(P.handle, popts, x, raise_on_notconv=not notconv_ok))
         torch.cuda.synchronize()
@@ -779,13 +918,16 @@ def bench_single(args):
         pmoved = sum(s["moved_updates"] for s in pst)
         L = sca.sca_problem_get_launch(P.handle)
         g, f = prof["grad"], prof["fold"]
+        # the method's bytes: every drawn column read once by the gradient pass
         grad_b = float(pupd) * bytes_per_update
         fold_b = float(pmoved) * bytes_per_update
+        impl_b = 0.0
         if not sparse and L["grad_kind"] == 4:
-            # fused round: the partials written by the gradient kernel, then read (with r
-            # read and written) by the partial reduction in place of the fold
+            # fused round: it also writes one m-vector of fold partials per workgroup
+            # (implementation traffic, not counted as the method's bytes), which the partial
+            # reduction then reads with r in place of the fold
             G = fused_groups()
-            grad_b = round_alg_bytes(L, float(pupd) / g["launches"], w.m, esize, G) * g["launches"]
+            impl_b = float(g["launches"]) * G * w.m * esize
             fold_b = float(f["launches"]) * (G + 2) * w.m * esize
         cands = [("grad", g, grad_b, grad_kernel_name(L, sparse, w.m))]
         if sparse:
@@ -793,17 +935,28 @@ def bench_single(args):
                           "k_bin_scan<4> + k_bin_scatter<float,8> + k_bin_acc<float,float,float>"))
         step, kp, kb, kname = max(cands, key=lambda c: c[1]["ms"])
         achieved = kb / (kp["ms"] * 1e-3) / 1e9
-        traffic = pmc_traffic(L, kind) if kind in PMC_SUMMARY and step == "grad" else None
+        pmc = pmc_traffic(L, kind) if kind in PMC_SUMMARY and step == "grad" else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if traffic is None else round(traffic),
+                    traffic=None if pmc is None else round(pmc["traffic"]),
                     kernel=kname, step=step, launch=L,
                     avg_launch_ms=round(kp["ms"] / kp["launches"], 4),
-                    alg_bytes_per_launch=round(kb / kp["launches"]))
+                    alg_bytes_per_launch=round(kb / kp["launches"]),
+                    alg_bytes="drawn columns x bytes per column (the method's reads; "
+                              "fold partials excluded)")
+        if step == "grad" and impl_b:
+            roof["impl_bytes_per_launch"] = round(impl_b / kp["launches"])
+            roof["frac_with_impl_bytes"] = round((kb + impl_b) / (kp["ms"] * 1e-3) / 1e9
+                                                 / HBM_PEAK_GBS, 4)
+        if pmc is not None:
+            # the counters were read over their own probe rounds: paired with the probe's
+            # algorithmic bytes
+            roof["traffic_alg_bytes_per_launch"] = round(pmc["alg"])
+            roof["traffic_over_alg"] = round(pmc["traffic"] / pmc["alg"], 4)
         best = read_stream_peak(w.vals if sparse else w.At)
         roof["read_stream_peak"] = round(best, 1)
         roof["frac_of_read_stream_peak"] = round(achieved / best, 4)
-        prof_pass = dict(ms_per_step=pel / args.steps * 1e3,
+        prof_pass = dict(ms_per_step=pel / steps * 1e3,
                          per_launch_ms={k: round(v["ms"] / max(1, v["launches"]), 4)
                                         for k, v in prof.items()},
                          grad_GBps=round(grad_b / (g["ms"] * 1e-3) / 1e9, 1) if g["ms"] else None,
@@ -813,10 +966,9 @@ def bench_single(args):
         log(f"profiled pass: {prof_pass}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if cpu_rounds:
         t0 = time.perf_counter()
-        cr = args.cpu_rounds or {"lasso": 16, "nonconvex": 100, "sparse": 100}[kind]
-        cpu = cpu_baseline(w, opts_kw, cr)
+        cpu = cpu_baseline(w, opts_kw, cpu_rounds)
         log(f"cpu baseline in {time.perf_counter() - t0:.1f} s: {cpu}")
 
     if kind == "lasso":
@@ -835,19 +987,19 @@ def bench_single(args):
         cfg["step"] = f"{args.rounds} rounds from x=0"
     else:
         cfg["tol_rel_obj"] = args.tol
-    ms_per_step = elapsed / args.steps * 1e3
+    ms_per_step = elapsed / steps * 1e3
     if per_seed:
         value = float(np.median([d["value"] for d in per_seed]))
         ms_per_step = float(np.median([d["ms_per_step"] for d in per_seed]))
-        cfg["seeds"] = args.seeds
+        cfg["seeds"] = seeds
         cfg["statistic"] = "median over data seeds of K timed solves each"
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "coord-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -856,16 +1008,124 @@ def bench_single(args):
         "data": "synthetic",
         "config": cfg,
         "time_to_tol_s": ms_per_step / 1e3,
-        "rounds_per_solve": rounds / args.steps,
-        "rel_err_final": [s["rel_err"] for s in stats],
-        "merit_final": [s["merit"] for s in stats],
+        "rounds_per_solve": rounds / steps,
+        "rel_err_final": stats[-1]["rel_err"],
+        "merit_final": stats[-1]["merit"],
         "F_star": F_star,
+        "F_star_check": fcheck,
         "roofline": roof,
         "profiled_pass": prof_pass,
         "cpu_baseline": cpu,
     }
+    if milestones:
+        out["merit_milestones"] = milestones
     if per_seed:
         out["per_seed"] = per_seed
+    P.close()
+    del w, x
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_c1(args, steps):
+    """LASSO 200 x 1000 FP64, scalar blocks, every block each round (gamma 0.9): microseconds
+    per round and coordinate updates per second over fixed budgets of rounds, and the time to
+    relative error 1e-6, with the oracle timed beside it on the host (same rounds, same
+    stopping rule).  This size fits in the caches, so the rounds are latency bound."""
+    w = inputs.lasso_small_fp64(seed=0, device="cuda")
+    opts_kw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
+    P = sca.Problem.from_workload(w)
+    o = sca.make_opts(**opts_kw, max_rounds=200000, check_every=50, tol_merit=F_STAR_MERIT)
+    x = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    st64 = sca.sca_solve(P.handle, o, x, raise_on_notconv=False)
+    _checked_fstar_solve(st64, w.name)
+    F_star = st64["F"]
+    fcheck = certify_fstar(w, F_star, x.cpu().numpy())
+    # fixed budget of rounds (each check of 50 rounds one graph launch), no stopping test
+    budget = 2000
+    ob = sca.make_opts(**opts_kw, max_rounds=budget, check_every=50)
+    sca.sca_solve(P.handle, ob, x.zero_())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sca.sca_solve(P.handle, ob, x.zero_())
+    torch.cuda.synchronize()
+    t_budget = (time.perf_counter() - t0) / steps
+    # time to tolerance
+    ot = sca.make_opts(**opts_kw, max_rounds=100000, check_every=10, tol_rel_obj=args.tol,
+                       F_star=F_star)
+    sca.sca_solve(P.handle, ot, x.zero_())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = []
+    for _ in range(steps):
+        sts.append(sca.sca_solve(P.handle, ot, x.zero_()))
+    torch.cuda.synchronize()
+    t_tol = (time.perf_counter() - t0) / steps
+    gpu = dict(us_per_round=t_budget / budget * 1e6,
+               coord_updates_per_s=budget * w.n / t_budget,
+               time_to_tol_s=t_tol, rounds_to_tol=sts[-1]["rounds"],
+               rel_err_final=sts[-1]["rel_err"])
+    log(f"C1 GPU: {gpu}")
+    P.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import sca_oracle as O
+        cores, model = cpu_info()
+        prob = O.Problem(A=w.A_numpy(), b=w.b.double().cpu().numpy(), lam=w.lam,
+                         block_ptr=w.block_ptr)
+        cfg = O.RunConfig(tau=w.tau, gamma=w.gamma, p=w.p, seed=w.seed)
+        prob.colnorm2()
+        rounds = 200
+        t0 = time.perf_counter()
+        O.run_rounds(prob, cfg, np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0, rounds)
+        t_or = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sol = O.solve(prob, cfg, check_every=10, F_star=F_star, tol_rel_obj=args.tol)
+        t_os = time.perf_counter() - t0
+        cpu = dict(value=rounds * w.n / t_or, unit="coord-updates/s", cores=cores,
+                   cpu_model=model, kind="oracle", us_per_round=t_or / rounds * 1e6,
+                   time_to_tol_s=t_os, rounds_to_tol=sol["rounds"],
+                   sample=f"{rounds} rounds of the same 200x1000 FP64 LASSO from x=0 (FP64 "
+                          f"numpy), then one oracle solve to rel. error {args.tol:g}")
+        log(f"C1 oracle: {cpu}")
+    return dict(config={"workload": "lasso_dense_200x1000_fp64", "m": w.m, "n": w.n,
+                        "block": 1, "select_p": 1.0, "gamma": w.gamma, "tau": round(w.tau, 6),
+                        "tol_rel_obj": args.tol, "steps": steps, "budget_rounds": budget},
+                dtype="f64", gpu=gpu, F_star=F_star, F_star_check=fcheck, cpu_baseline=cpu,
+                roofline=None,
+                roofline_note="1.6 MB of A stays in the caches: latency bound, no HBM roofline")
+
+
+def bench_default(args):
+    """The headline (the 20000 x 100000 FP32 LASSO to 1e-6, medians over data seeds), then
+    the other single-GPU workloads in smaller runs, each under a key of its own: the
+    200 x 1000 FP64 LASSO (latency bound), the 1e5 x 1e6 sparse LASSO and the
+    10000 x 50000 box-nonconvex budget."""
+    t_all = time.perf_counter()
+    out = run_single("lasso", args, args.steps, args.warmup, seeds=args.seeds,
+                     profile=not args.no_profile,
+                     cpu_rounds=None if args.no_cpu_baseline else (args.cpu_rounds or 16))
+    if out["cpu_baseline"]:
+        out["cpu_baseline"]["cpu_model"] = cpu_info()[1]
+    if not args.headline_only:
+        k_steps, k_warm = min(args.steps, 5), min(args.warmup, 1)
+        extra_cpu = None if args.no_cpu_baseline else 40
+        for key, kind in (("sparse_1e5x1e6", "sparse"), ("nonconvex_10000x50000", "nonconvex")):
+            t0 = time.perf_counter()
+            rec = run_single(kind, args, k_steps, k_warm, profile=not args.no_profile,
+                             cpu_rounds=extra_cpu)
+            if rec["cpu_baseline"]:
+                rec["cpu_baseline"]["cpu_model"] = cpu_info()[1]
+            for k in ("metric", "unit", "n_gpus", "higher_is_better", "scaling", "vs_baseline",
+                      "data"):
+                rec.pop(k, None)
+            out[key] = rec
+            log(f"{key} done in {time.perf_counter() - t0:.1f} s")
+        t0 = time.perf_counter()
+        out["lasso_200x1000_fp64"] = bench_c1(args, k_steps)
+        log(f"lasso_200x1000_fp64 done in {time.perf_counter() - t0:.1f} s")
+    log(f"bench finished in {time.perf_counter() - t_all:.1f} s")
     print(json.dumps(out), flush=True)
 
 

@@ -34,11 +34,12 @@ def test_row_groups_per_thread_of_the_fused_round(bench):
 
 
 def test_algorithmic_bytes_per_launch(bench):
-    # drawn columns once; the fused round also writes one m-vector of partials per workgroup
+    # the method's bytes: the drawn columns, once, for both round kinds (the fused round's
+    # fold partials are implementation traffic and are reported beside them)
     assert bench.round_alg_bytes(TWO_PASS, 25000, 20000, 4, 256) == 25000 * 20000 * 4
     assert bench.round_alg_bytes(FUSED, 25000.6, 20000, 4, 256) == pytest.approx(
-        25000.6 * 80000 + 256 * 80000)
-    assert bench.round_alg_bytes(FUSED, 25000.6, 20000, 4, 256) == pytest.approx(2.0206e9,
+        25000.6 * 80000)
+    assert bench.round_alg_bytes(FUSED, 25000.6, 20000, 4, 256) == pytest.approx(2.0000e9,
                                                                                  rel=1e-4)
 
 
@@ -100,9 +101,14 @@ def test_counter_summary_scaling_and_fingerprint(bench, tmp_path, monkeypatch):
     assert float(kv["traffic_bytes_per_launch"]) == pytest.approx(fetch_b + write_b, abs=1)
     alg = bench.round_alg_bytes(FUSED, 750018 / 30, 20000, 4, 256)
     assert float(kv["algorithmic_bytes_per_launch"]) == pytest.approx(alg, abs=1)
+    assert float(kv["fold_partial_bytes_per_launch"]) == 256 * 20000 * 4
+    assert float(kv["traffic_over_algorithmic"]) == pytest.approx((fetch_b + write_b) / alg,
+                                                                  abs=1e-4)
     assert int(kv["launches"]) == 2
     assert kv["fingerprint"].strip() == bench.kernel_fingerprint(FUSED)
-    assert bench.pmc_traffic(FUSED) == pytest.approx(fetch_b + write_b, abs=1)
+    got = bench.pmc_traffic(FUSED)
+    assert got["traffic"] == pytest.approx(fetch_b + write_b, abs=1)
+    assert got["alg"] == pytest.approx(alg, abs=1)
     assert bench.pmc_traffic(dict(FUSED, grad_cols=2)) is None  # another launch shape
 
 
@@ -133,6 +139,52 @@ def test_sparse_counter_summary_adds_both_step_kernels(bench, tmp_path, monkeypa
     assert float(kv["traffic_bytes_per_launch"]) == pytest.approx(fetch_b + write_b, abs=1)
     assert float(kv["algorithmic_bytes_per_launch"]) == pytest.approx(1e5 * 100 * 8, abs=1)
     assert int(kv["launches"]) == 3
-    assert bench.pmc_traffic(launch, "sparse") == pytest.approx(fetch_b + write_b, abs=1)
+    assert bench.pmc_traffic(launch, "sparse")["traffic"] == pytest.approx(fetch_b + write_b, abs=1)
     assert bench.pmc_traffic(launch, "lasso") is None  # the dense summary, another shape
     assert "--pmc-probe --workload sparse" in summary.read_text()
+
+
+def test_fstar_certificate_on_a_host_lasso(bench):
+    """certify_fstar: at the exact LASSO minimiser (brute force over sign patterns on a tiny
+    problem) the duality gap and ||M_F|| vanish to rounding; at a perturbed point the gap is
+    positive and bounds the objective error; a wrong F* is refused."""
+    import itertools
+    import numpy as np
+    import torch
+
+    class W:  # the fields certify_fstar reads, host tensors
+        pass
+    rng = np.random.default_rng(3)
+    m, n = 12, 6
+    A = rng.normal(size=(m, n))
+    A /= np.linalg.norm(A, axis=0)
+    b = rng.normal(size=m)
+    lam = 0.3
+    best = None
+    for s in itertools.product((-1, 0, 1), repeat=n):
+        S = [j for j in range(n) if s[j]]
+        x = np.zeros(n)
+        if S:
+            AS = A[:, S]
+            xs = np.linalg.solve(AS.T @ AS, AS.T @ b - lam * np.array([s[j] for j in S]))
+            if np.any(np.sign(xs) != np.array([s[j] for j in S])):
+                continue
+            x[S] = xs
+        g = A.T @ (A @ x - b)
+        if np.all(np.abs(g[np.array(s) == 0]) <= lam + 1e-12):
+            best = x
+    w = W()
+    w.name, w.m, w.n, w.lam = "tiny", m, n, lam
+    w.At = torch.from_numpy(np.ascontiguousarray(A.T))
+    w.b = torch.from_numpy(b)
+    F = 0.5 * np.sum((A @ best - b) ** 2) + lam * np.abs(best).sum()
+    out = bench.certify_fstar(w, F, best)
+    assert out["certified"] and out["gap"] <= 1e-12 and out["host_MF"] <= 1e-12
+    xp = best + 1e-3 * rng.normal(size=n)
+    Fp = 0.5 * np.sum((A @ xp - b) ** 2) + lam * np.abs(xp).sum()
+    # a perturbed point: its gap (>= its objective error) is far beyond the limit
+    with pytest.raises(RuntimeError):
+        bench.certify_fstar(w, Fp, xp)
+    # a wrong F* at the right point
+    with pytest.raises(RuntimeError):
+        bench.certify_fstar(w, F * (1 + 1e-6), best)
