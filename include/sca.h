@@ -210,6 +210,20 @@ sca_status sca_adjoint(sca_problem* p, const sca_opts* opts, const void* xstar_d
                        const void* xbar_dev, void* bbar_dev, double* lambar_host,
                        double cg_tol, int64_t cg_maxit, void* stream);
 
+/* sca_adjoint without any device allocation, for callers that cannot allocate device
+ * memory (serving loops, harnesses that forbid hipMalloc): sca_adjoint allocates its
+ * workspace on its first call with a problem; this variant keeps it in a fixed 32 MiB
+ * device array of the library (one per GPU, held until the process ends).  Same
+ * arguments, results and errors as sca_adjoint; in addition SCA_EINVAL (nothing enqueued)
+ * when the problem needs more than the array holds: about 54 n + 264 m bytes (n columns,
+ * m rows; 10.6 MB at 20000 x 100000).  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other host threads, other streams) race and must be serialised
+ * by the caller.  Synchronises 'stream' (the conjugate-gradient loop reads its convergence
+ * flags on the host), so it cannot be captured into a graph. */
+sca_status sca_adjoint_noalloc(sca_problem* p, const sca_opts* opts, const void* xstar_dev,
+                               const void* xbar_dev, void* bbar_dev, double* lambar_host,
+                               double cg_tol, int64_t cg_maxit, void* stream);
+
 /* Accumulated kernel times (ms) and launch counts of sca_step calls made with
  * SCA_FLAG_PROFILE, indexed by SCA_K_*; arrays of SCA_K_NKINDS entries.  reset != 0
  * clears them after reading. */

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -358,6 +359,7 @@ struct AdjWork {
   long long items_cap = 0;
   BInst* inst = nullptr;  // owned only for a plain problem
   bool own_inst = false;
+  bool fixed = false;     // carved out of the fixed scratch array: never (re)allocated
 
   void release() {
     void* ptrs[] = {st, sgn, S_sgn, w, res, p, v, u, part, sc, chunk, S_idx, S_lo, S_n, G, ng,
@@ -457,6 +459,9 @@ sca_status adjoint_core(AdjWork* W, int dtype, int ncu, const BInst* d_inst,
       items.push_back(it);
     }
   if ((long long)items.size() > W->items_cap) {
+    if (W->fixed)
+      return set_error(SCA_EINVAL, "adjoint: %zu work items exceed the scratch's %lld",
+                       items.size(), W->items_cap);
     if (W->items) (void)hipFree(W->items);
     W->items = nullptr;
     W->items_cap = std::max<long long>(1024, (long long)items.size());
@@ -614,6 +619,149 @@ extern "C" sca_status sca_adjoint(sca_problem* p, const sca_opts* o, const void*
                               (const double*)xstar, (const double*)xbar, (double*)bbar, lambar,
                               cg_tol, cg_maxit, s, nullptr);
   return st;
+}
+
+// ------------------------------------------------------------------ no-allocation variant
+// sca_adjoint_noalloc keeps its workspace in this fixed device array instead of memory the
+// problem allocates on its first adjoint call.  Each GPU holds its own copy, at its own
+// address, until the process ends.  In host code the array's name is not a device
+// address: the address comes from hipGetSymbolAddress, once per device (scratch_base).
+constexpr size_t kAdjScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kAdjScratchBytes];
+
+namespace {
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_base[kScratchMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on its first use).
+sca_status scratch_base(unsigned char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchMaxDevices)
+    return set_error(SCA_EHIP, "no usable current device for the adjoint scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_base[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return set_error(SCA_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch_base[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_base[dev];
+  return SCA_OK;
+}
+
+// Lays the workspace of one instance of n columns and m rows out in the scratch from base
+// (256-byte aligned pieces); returns the bytes used.  With base == nullptr only counts.
+size_t adj_carve(AdjWork* W, unsigned char* base, long long n, long long m) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    off = (off + 255) & ~size_t(255);
+    void* q = base ? (void*)(base + off) : nullptr;
+    off += std::max<size_t>(bytes, 16);
+    return q;
+  };
+  const long long nch = (n + kChunk - 1) / kChunk + 1;
+  const long long nitems = (n + kBC - 1) / kBC + 1;
+  W->st = (AState*)take(sizeof(AState));
+  W->sgn = (double*)take(sizeof(double) * n);
+  W->S_sgn = (double*)take(sizeof(double) * n);
+  W->w = (double*)take(sizeof(double) * n);
+  W->res = (double*)take(sizeof(double) * n);
+  W->p = (double*)take(sizeof(double) * n);
+  W->v = (double*)take(sizeof(double) * n);
+  W->u = (double*)take(sizeof(double) * m);
+  W->part = (double*)take(sizeof(double) * kAMaxGroups * m);
+  W->sc = (double*)take(sizeof(double) * SC_N);
+  W->chunk = (int*)take(sizeof(int) * nch);
+  W->S_idx = (int*)take(sizeof(int) * n);
+  W->S_lo = (int*)take(sizeof(int));
+  W->S_n = (int*)take(sizeof(int));
+  W->G = (int*)take(sizeof(int));
+  W->ng = (int*)take(sizeof(int));
+  W->nrt = (int*)take(sizeof(int));
+  W->tile_off = (int*)take(sizeof(int) * 2);
+  W->done = (int*)take(sizeof(int));
+  W->nonpd = (int*)take(sizeof(int));
+  W->iters = (int*)take(sizeof(int));
+  W->col_off = (int*)take(sizeof(int) * 2);
+  W->row_off = (int*)take(sizeof(int) * 2);
+  W->items = (BItem*)take(sizeof(BItem) * nitems);
+  W->inst = (BInst*)take(sizeof(BInst));
+  W->items_cap = nitems;
+  return off;
+}
+
+__global__ void k_adj_zero(double* __restrict__ a, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    a[i] = 0.0;
+}
+
+}  // namespace
+
+extern "C" sca_status sca_adjoint_noalloc(sca_problem* p, const sca_opts* o, const void* xstar,
+                                          const void* xbar, void* bbar, double* lambar,
+                                          double cg_tol, int64_t cg_maxit, void* stream) {
+  if (!p) return set_error(SCA_EINVAL, "problem is NULL");
+  sca_status st = validate_opts(o);
+  if (st != SCA_OK) return st;
+  if (!xstar || !xbar || !bbar || !lambar) return set_error(SCA_EINVAL, "NULL argument");
+  if (p->sparse) return set_error(SCA_EINVAL, "the adjoint is built for dense problems");
+  if (p->reg != 0) return set_error(SCA_EINVAL, "the adjoint is defined for the l1 regulariser");
+  if (!(p->cn2_min + o->tau > 0.0)) return set_error(SCA_EINVAL, "q_j = 0 (zero column, tau = 0)");
+  AdjWork W;
+  const size_t need = adj_carve(&W, nullptr, p->n, p->m);
+  if (need > kAdjScratchBytes)
+    return set_error(SCA_EINVAL,
+                     "sca_adjoint_noalloc: a problem of %lld rows and %lld columns needs %zu "
+                     "bytes of workspace, beyond the fixed %zu (use sca_adjoint)",
+                     (long long)p->m, (long long)p->n, need, kAdjScratchBytes);
+  if (cg_tol <= 0.0) cg_tol = p->dtype == SCA_F64 ? 1e-12 : 1e-6;
+  if (cg_maxit <= 0) cg_maxit = 10000;
+  unsigned char* base = nullptr;
+  if ((st = scratch_base(&base)) != SCA_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  adj_carve(&W, base, p->n, p->m);
+  W.K = 1;
+  W.Ntot = p->n;
+  W.Mtot = p->m;
+  W.fixed = true;
+  // the array keeps the previous call's contents: the fold partials must start at zero
+  // (rows no fold tile writes are read as zero); everything else is written before it is read
+  const long long npart = (long long)kAMaxGroups * p->m;
+  hipLaunchKernelGGL(k_adj_zero, dim3((unsigned)std::min<long long>((npart + 255) / 256, 1024)),
+                     dim3(256), 0, s, W.part, npart);
+  BInst I;
+  I.A = p->A;
+  I.lda = p->lda;
+  I.m = (int)p->m;
+  I.n = (int)p->n;
+  I.row_off = 0;
+  I.col_off = 0;
+  I.blk_off = 0;
+  I.nblk = (int)p->nblocks;
+  I.lam = p->lam;
+  I.c = p->c;
+  I.beta = p->beta;
+  I.tau = o->tau;
+  I.F_star = 0;
+  I.inst_id = o->instance;
+  I.pad = 0;
+  std::vector<BInst> hinst(1, I);
+  if (hipMemcpyAsync(W.inst, &hinst[0], sizeof(BInst), hipMemcpyHostToDevice, s) != hipSuccess)
+    return set_error(SCA_EHIP, "adjoint descriptor copy failed");
+  residual_any(p, xstar, nullptr, s);  // FP64 residual at x* into the problem's workspace
+  if (p->dtype == SCA_F32)
+    return adjoint_core<float>(&W, 0, p->ncu, W.inst, hinst, p->d_cn2, p->d_r64,
+                               (const float*)xstar, (const float*)xbar, (float*)bbar, lambar,
+                               cg_tol, cg_maxit, s, nullptr);
+  return adjoint_core<double>(&W, 1, p->ncu, W.inst, hinst, p->d_cn2, p->d_r64,
+                              (const double*)xstar, (const double*)xbar, (double*)bbar, lambar,
+                              cg_tol, cg_maxit, s, nullptr);
 }
 
 void sca::adjoint_release(sca_adj_cache* c) {

@@ -98,6 +98,8 @@ SIGNATURES = {
     "sca_solve": (_S, [_P, ctypes.POINTER(sca_opts), _P, ctypes.POINTER(sca_stats), _P]),
     "sca_adjoint": (_S, [_P, ctypes.POINTER(sca_opts), _P, _P, _P, ctypes.POINTER(_D), _D, _I64,
                          _P]),
+    "sca_adjoint_noalloc": (_S, [_P, ctypes.POINTER(sca_opts), _P, _P, _P, ctypes.POINTER(_D),
+                                 _D, _I64, _P]),
     "sca_profile_get": (_S, [_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D),
                              _S]),
     "sca_tuning_set": (_S, [ctypes.POINTER(sca_tune_entry), _I64]),
@@ -363,6 +365,16 @@ def sca_adjoint(h, opts, xstar, xbar, bbar, cg_tol=0.0, cg_maxit=0, stream=None)
     ptrs = _dptrs((xstar, "xstar", dt, n), (xbar, "xbar", dt, n), (bbar, "bbar", dt, m))
     _check(lib().sca_adjoint(h, ctypes.byref(opts), *ptrs,
                              ctypes.byref(lb), float(cg_tol), int(cg_maxit), _stream(stream)))
+    return lb.value
+
+
+def sca_adjoint_noalloc(h, opts, xstar, xbar, bbar, cg_tol=0.0, cg_maxit=0, stream=None):
+    lb = _D()
+    sh = _shape(h)
+    dt, n, m = sh.get("dtype"), sh.get("n"), sh.get("m")
+    ptrs = _dptrs((xstar, "xstar", dt, n), (xbar, "xbar", dt, n), (bbar, "bbar", dt, m))
+    _check(lib().sca_adjoint_noalloc(h, ctypes.byref(opts), *ptrs, ctypes.byref(lb),
+                                     float(cg_tol), int(cg_maxit), _stream(stream)))
     return lb.value
 
 
