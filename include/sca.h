@@ -255,10 +255,12 @@ typedef struct {
   int32_t grad_wg_per_cu;
 } sca_launch;
 
-/* One row of the tuning table: problems of this dtype with m_lo <= m <= m_hi get 'launch'. */
+/* One row of the tuning table.  target 0: single problems of this dtype with
+ * m_lo <= m <= m_hi get 'launch' (the shapes above); target 1: batches of this dtype whose
+ * largest instance has m_lo <= m <= m_hi get 'launch' (the shapes of sca_batch_set_launch). */
 typedef struct {
   int32_t dtype; /* sca_dtype */
-  int32_t reserved;
+  int32_t target; /* 0: single problem, 1: batch */
   int64_t m_lo, m_hi;
   sca_launch launch;
 } sca_tune_entry;
@@ -319,6 +321,22 @@ void sca_batch_destroy(sca_batch* batch);
 /* Offsets (count+1 entries each, host) of every instance in the concatenated x and r. */
 sca_status sca_batch_layout(sca_batch* batch, int64_t* x_offsets_host, int64_t* r_offsets_host);
 
+/* Launch shape of the batch's rounds (Algorithm 1, steps S.1-S.5 of every instance).
+ *  grad_kind 1: fused round -- one pass over the drawn columns: a 256-thread workgroup holds
+ *    a group of columns of one instance, that instance's r and its own fold partial in
+ *    registers (512 threads, Q = 1, 2 or 4 row groups of 16 bytes per thread as the
+ *    instance's m needs, and 4/Q columns per group: grad_cols = 4 registers of 16 bytes per
+ *    thread and group); the workgroups (grad_wg_per_cu in [1, 4] per compute unit) take contiguous
+ *    shares of the round's work cut by cost (rows + 512 per drawn column), so the sums have a
+ *    fixed order; a second kernel adds the partials of instances that were shared between
+ *    workgroups.  Needs every instance's m <= 8192 (FP32) or <= 4096 (FP64).
+ *  grad_kind 0: two-pass round (gradient pass, then an ordered fold of the moved columns).
+ * A new batch takes the tuning table's first target-1 row matching its dtype and largest m,
+ * else the fused kind (grad_wg_per_cu 2) where it fits and the two-pass kind otherwise.
+ * set rejects a shape outside these (SCA_EINVAL); grad_unroll is ignored. */
+sca_status sca_batch_get_launch(sca_batch* batch, sca_launch* out);
+sca_status sca_batch_set_launch(sca_batch* batch, const sca_launch* launch);
+
 /* Regulariser shared by every instance (as sca_problem_set_regularizer). */
 sca_status sca_batch_set_regularizer(sca_batch* batch, sca_reg reg, double theta);
 
@@ -335,10 +353,13 @@ sca_status sca_batch_step(sca_batch* batch, const sca_opts* opts, int64_t round_
                           int64_t nrounds, void* x_all_dev, void* r_all_dev, void* stream);
 
 /* Solve every instance from x_all (in: x^0, out: x).  Rounds run in graph launches of
- * check_every rounds followed by a fresh FP64 residual and, per instance, the tests
- * (F - F_star)/|F_star| <= tol_rel_obj and (when tol_merit > 0, at the cost of a full
- * pass over every A) ||xh(x) - x||_inf <= tol_merit; a converged instance stops drawing
- * blocks.  stats
+ * check_every rounds followed by, per instance, the test (F - F_star)/|F_star| <=
+ * tol_rel_obj (Section 4.2) on the running residual, confirmed for the instances that pass
+ * with a fresh FP64 residual of their own columns (a failed confirmation restarts that
+ * instance's running residual from the fresh one), as sca_solve does; when tol_merit > 0
+ * instead a fresh FP64 residual of every instance, both tests on it and, at the cost of a
+ * full pass over every A, ||xh(x) - x||_inf <= tol_merit (Section 4.3).  A converged
+ * instance stops drawing blocks.  stats
  * (count entries, may be NULL) receive per-instance results (coord_updates per instance;
  * moved_updates is the batch-wide total of moved coordinates, the same in every entry).
  * Synchronises 'stream';

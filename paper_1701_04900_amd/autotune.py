@@ -1,13 +1,21 @@
-"""Autotuner of the dense round's launch shape.
+"""Autotuner of the round's launch shape, for single dense problems and for batches.
 
-For each (dtype, m range) bucket it draws a representative problem (N(0,1), unit columns,
-blocks of 64, a quarter of the blocks per round), runs a few rounds with every candidate
-shape through sca_problem_set_launch, times the gradient, compaction and fold kernels of
-the round with the library's HIP events and keeps the shape with the shortest sum (the
-fused kind does the fold's work inside its gradient kernel).  The table is written as JSON next to this file
-(tuning/gfx950.json) and installed by the binding when the library is loaded.
+Single problems: for each (dtype, m range) bucket it draws a representative problem (N(0,1),
+unit columns, blocks of 64, a quarter of the blocks per round), runs a few rounds with every
+candidate shape through sca_problem_set_launch, times the gradient, compaction and fold
+kernels of the round with the library's HIP events and keeps the shape with the shortest
+sum (the fused kind does the fold's work inside its gradient kernel).
 
-    python -m paper_1701_04900_amd.autotune [--out PATH] [--rounds R]
+Batches: for each dtype it draws a representative batch (instances of uneven m up to the
+fused kind's limit, n = 5m, blocks of 64, a quarter of the blocks per round) and times whole
+batched rounds (sca_batch_step, HIP events on the stream) for the two-pass kind and the
+fused kind on 1 to 4 workgroups per compute unit, in two phases -- the first rounds from
+x = 0 and rounds after a few hundred -- and keeps the shape with the shortest sum.
+
+The table is written as JSON next to this file (tuning/gfx950.json) and installed by the
+binding when the library is loaded.
+
+    python -m paper_1701_04900_amd.autotune [--out PATH] [--rounds R] [--only single|batch]
 """
 from __future__ import annotations
 
@@ -53,9 +61,69 @@ def _time_shape(P, w, opts, shape, rounds):
     return sum(pr[k]["ms"] for k in ("grad", "compact", "fold")) / rounds
 
 
-def tune(out_path=sca.TUNING_PATH, rounds=30, log=print):
+# batch candidates: (kind, workgroups per CU); (dtype, m_lo, m_hi, instances, m range)
+BATCH_CANDIDATES = [(0, 2), (1, 1), (1, 2), (1, 3), (1, 4)]
+BATCH_BUCKETS = [("f32", 1, 8192, 48, (500, 8000)), ("f64", 1, 4096, 48, (250, 4000))]
+
+
+def _time_batch_shape(B, ws, shape, rounds, skip):
+    """Milliseconds per batched round (HIP events around sca_batch_step), summed over the
+    first rounds from x = 0 and rounds after `skip` more."""
+    kind, wg = shape
+    sca.sca_batch_set_launch(B.handle, kind, 4, wg)
+    dt = ws[0].dtype
+    o = sca.make_opts(gamma=0.9, select_p=0.25, seed=1)
+    x = torch.zeros(int(B.xoff[-1]), dtype=dt, device="cuda")
+    r = torch.zeros(int(B.roff[-1]), dtype=dt, device="cuda")
+    sca.sca_batch_residual(B.handle, x, r)
+    total = 0.0
+    k = 0
+    for phase in range(2):
+        if phase == 1:
+            sca.sca_batch_step(B.handle, o, k, skip, x, r)
+            k += skip
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sca.sca_batch_step(B.handle, o, k, rounds, x, r)
+        e1.record()
+        torch.cuda.synchronize()
+        k += rounds
+        total += e0.elapsed_time(e1) / rounds
+    return total
+
+
+def tune_batch(rounds=20, skip=300, log=print):
     entries = []
-    for dt, lo, hi, m, n in BUCKETS:
+    for dt, lo, hi, count, mr in BATCH_BUCKETS:
+        dtype = torch.float32 if dt == "f32" else torch.float64
+        ws = inputs.batch_lasso(count, m_range=mr, nnz_frac=0.02, lam_range=(1e-3, 1e-1),
+                                block=64, p=0.25, dtype=dtype, seed=1, device="cuda")
+        B = sca.Batch(ws)
+        res = []
+        for shape in BATCH_CANDIDATES:
+            res.append((_time_batch_shape(B, ws, shape, rounds, skip), shape))
+        res.sort()
+        ms, best = res[0]
+        log(f"batch {dt} ({count} instances, m in {mr}): " +
+            ", ".join(f"{s}: {t:.3f} ms" for t, s in sorted(res, key=lambda v: v[1])) +
+            f" -> {best}")
+        entries.append(dict(target="batch", dtype=dt, m_lo=lo, m_hi=hi, grad_kind=best[0],
+                            grad_cols=4, grad_unroll=1, grad_wg_per_cu=best[1],
+                            ms=round(ms, 5), probe=dict(instances=count, m_range=list(mr))))
+        B.close()
+        del ws
+        torch.cuda.empty_cache()
+    return entries
+
+
+def tune(out_path=sca.TUNING_PATH, rounds=30, log=print, only=None):
+    entries = []
+    old = []
+    if os.path.exists(out_path):
+        old = json.load(open(out_path)).get("entries", [])
+    if only == "batch":  # keep the single-problem rows
+        entries = [e for e in old if e.get("target") != "batch"]
+    for dt, lo, hi, m, n in (BUCKETS if only != "batch" else []):
         dtype = torch.float32 if dt == "f32" else torch.float64
         w = inputs.dense_problem(m, n, nnz_frac=0.01, lam_frac=0.01, block=64, p=0.25,
                                  dtype=dtype, seed=1, device="cuda")
@@ -81,6 +149,10 @@ def tune(out_path=sca.TUNING_PATH, rounds=30, log=print):
         P.close()
         del w
         torch.cuda.empty_cache()
+    if only != "single":
+        entries += tune_batch(log=log)
+    else:
+        entries += [e for e in old if e.get("target") == "batch"]
     os.makedirs(os.path.dirname(out_path), exist_ok=True)
     with open(out_path, "w") as f:
         json.dump(dict(device="gfx950", created=time.strftime("%Y-%m-%d"), entries=entries), f,
@@ -92,11 +164,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=sca.TUNING_PATH)
     ap.add_argument("--rounds", type=int, default=30)
+    ap.add_argument("--only", choices=["single", "batch"], default=None)
     args = ap.parse_args()
     torch.cuda.set_device(0)
     sca.lib()
     sca.sca_tuning_set([])  # measure every shape from the built-in default
-    tune(args.out, args.rounds, log=lambda s: print(s, flush=True))
+    tune(args.out, args.rounds, log=lambda s: print(s, flush=True), only=args.only)
 
 
 if __name__ == "__main__":

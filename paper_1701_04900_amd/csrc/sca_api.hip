@@ -115,14 +115,20 @@ static bool launch_valid(const sca_launch* l) {
   }
 }
 
-// Fused round (k_grad_br_fold): Q row groups of 16 bytes per thread of a 1024-thread
-// workgroup hold a whole column; 0 when the problem is sparse or its columns are too long
-// for the registers (FP32: Q <= 5, m <= 20480; FP64: Q <= 3, m <= 6144).
+// Fused round (k_grad_br_fold): q row groups of 16 bytes per thread of a 1024-thread
+// workgroup hold a whole column, in registers up to the register limit (FP32: 5, m <= 20480;
+// FP64: 3, m <= 6144) and beyond it in thread-private LDS slots (FP32: 4 in registers and 2
+// or 3 in LDS, m <= 28672 -- 5 + 3 would spill registers; FP64: 3 + 1..3, m <= 12288); 0
+// when the problem is sparse or its columns are longer.
+static int fused_qmax_regs(const sca_problem* p) {
+  return p->esize == 4 ? kFusedMaxQ32 : kFusedMaxQ64;
+}
 static int fused_q(const sca_problem* p) {
   if (p->sparse) return 0;
   const int64_t vn = 16 / (int64_t)p->esize;
   const int64_t q = ((p->m + vn - 1) / vn + 1023) / 1024;
-  return q <= (p->esize == 4 ? kFusedMaxQ32 : kFusedMaxQ64) ? (int)q : 0;
+  const int64_t qmax = p->esize == 4 ? 7 : kFusedMaxQ64 + kFusedMaxL;
+  return q <= qmax ? (int)q : 0;
 }
 
 // Workgroups (= fold partials) of the fused round: one per compute unit, at most 256
@@ -132,6 +138,7 @@ static int fused_groups(const sca_problem* p) { return std::max(1, std::min(p->n
 // Largest column group whose registers fit (without spills) next to Q row groups of r and
 // of the partial (two buffers of C columns).
 static int fused_cmax(const sca_problem* p, int q) {
+  if (q > fused_qmax_regs(p)) return 1;
   if (p->esize == 4) return q == 1 ? 8 : q == 2 ? 4 : q == 3 ? 2 : 1;
   return q == 1 ? 4 : q == 2 ? 2 : 1;
 }
@@ -155,19 +162,36 @@ static std::vector<sca_tune_entry> g_tuning;
 
 extern "C" sca_status sca_tuning_set(const sca_tune_entry* e, int64_t count) {
   if (count < 0 || (count > 0 && !e)) return set_error(SCA_EINVAL, "bad tuning table");
-  for (int64_t i = 0; i < count; ++i)
-    if (!launch_valid(&e[i].launch) || e[i].m_lo > e[i].m_hi ||
-        (e[i].dtype != SCA_F32 && e[i].dtype != SCA_F64))
+  for (int64_t i = 0; i < count; ++i) {
+    const sca_launch& l = e[i].launch;
+    const bool batch_ok = l.struct_size == sizeof(sca_launch) &&
+                          (l.grad_kind == 0 ||
+                           (l.grad_kind == 1 && l.grad_cols == 4 &&
+                            l.grad_wg_per_cu >= 1 && l.grad_wg_per_cu <= 4));
+    const bool ok_launch = e[i].target == 0 ? launch_valid(&l) : e[i].target == 1 && batch_ok;
+    if (!ok_launch || e[i].m_lo > e[i].m_hi || (e[i].dtype != SCA_F32 && e[i].dtype != SCA_F64))
       return set_error(SCA_EINVAL, "tuning row %lld is invalid", (long long)i);
+  }
   g_tuning.assign(e, e + count);
   return SCA_OK;
 }
 
 void sca::apply_tuning(sca_problem* p) {
   for (const sca_tune_entry& e : g_tuning) {
-    if (e.dtype == p->dtype && p->m >= e.m_lo && p->m <= e.m_hi && take_launch(p, &e.launch))
+    if (e.target == 0 && e.dtype == p->dtype && p->m >= e.m_lo && p->m <= e.m_hi &&
+        take_launch(p, &e.launch))
       return;
   }
+}
+
+bool sca::batch_tuning(int dtype, int64_t mmax, sca_launch* out) {
+  for (const sca_tune_entry& e : g_tuning) {
+    if (e.target == 1 && e.dtype == dtype && mmax >= e.m_lo && mmax <= e.m_hi) {
+      *out = e.launch;
+      return true;
+    }
+  }
+  return false;
 }
 
 extern "C" sca_status sca_problem_get_launch(sca_problem* p, sca_launch* out) {
@@ -575,7 +599,8 @@ static void fold_dense(sca_problem* p, RoundState* st, const int* list, const T*
 // 32 blocks and a workgroup's share of the drawn list fits its LDS list.
 static bool fused_draws(const sca_problem* p) {
   const int64_t G = fused_groups(p);
-  return p->nblocks <= kFusedSelBlocks && (p->n + G - 1) / G <= kFusedSelCols;
+  const int64_t cap = fused_q(p) > fused_qmax_regs(p) ? kFusedSelColsL : kFusedSelCols;
+  return p->nblocks <= kFusedSelBlocks && (p->n + G - 1) / G <= cap;
 }
 
 // S.1-S.5 fused (k_grad_br_fold, one workgroup per compute unit, S.1 inside when
@@ -592,7 +617,17 @@ static void grad_fold_dense(sca_problem* p, T* x, const T* r_read, const T* base
   hipLaunchKernelGGL((k_grad_br_fold<T, QQ, CC>), dim3(G), dim3(1024), 0, s, (const T*)p->A, \
                      (long long)p->lda, m, r_read, x, p->d_cn2, list, st, (T*)p->d_part,      \
                      (long long)p->ldp, bp, fs)
+#define FUSED_L(QQ, LL)                                                                     \
+  hipLaunchKernelGGL((k_grad_br_fold<T, QQ, 1, LL>), dim3(G), dim3(1024), 0, s,             \
+                     (const T*)p->A, (long long)p->lda, m, r_read, x, p->d_cn2, list, st,     \
+                     (T*)p->d_part, (long long)p->ldp, bp, fs)
   if constexpr (sizeof(T) == 4) {
+    if (q > kFusedMaxQ32) {  // 4 row groups in registers, the rest in LDS
+      if (q == 6)
+        FUSED_L(4, 2);
+      else
+        FUSED_L(4, 3);
+    } else {
     switch (q * 16 + c) {
       case 16 + 8: FUSED(1, 8); break;
       case 16 + 4: FUSED(1, 4); break;
@@ -606,7 +641,16 @@ static void grad_fold_dense(sca_problem* p, T* x, const T* r_read, const T* base
       case 64 + 1: FUSED(4, 1); break;
       default: FUSED(5, 1); break;
     }
+    }
   } else {
+    if (q > kFusedMaxQ64) {
+      if (q == kFusedMaxQ64 + 1)
+        FUSED_L(kFusedMaxQ64, 1);
+      else if (q == kFusedMaxQ64 + 2)
+        FUSED_L(kFusedMaxQ64, 2);
+      else
+        FUSED_L(kFusedMaxQ64, 3);
+    } else {
     switch (q * 16 + c) {
       case 16 + 4: FUSED(1, 4); break;
       case 16 + 2: FUSED(1, 2); break;
@@ -615,8 +659,10 @@ static void grad_fold_dense(sca_problem* p, T* x, const T* r_read, const T* base
       case 32 + 1: FUSED(2, 1); break;
       default: FUSED(3, 1); break;
     }
+    }
   }
 #undef FUSED
+#undef FUSED_L
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_FOLD);
   constexpr int VN = V16<T>::N;

@@ -35,77 +35,147 @@ __device__ __forceinline__ int upper_idx(const int* __restrict__ off, int K, int
 }
 
 // ------------------------------------------------------------------ S.1 over all instances
+// Cost of one drawn column in the split of the fused round's work: its rows plus a fixed
+// part for the per-column work that does not scale with m.
+constexpr int kBFColCost = 512;
+
 __global__ void __launch_bounds__(1024)
 k_bsel_count(int Btot, const int* __restrict__ blk_inst, const int* __restrict__ blk_len,
              const BInst* __restrict__ inst, const int* __restrict__ active, uint64_t seed,
              uint64_t T, const BState* __restrict__ st, int* __restrict__ blk_cols,
              int* __restrict__ chunk_cols, int* __restrict__ chunk_items,
-             long long* __restrict__ inst_upd) {
+             long long* __restrict__ chunk_cost, int* __restrict__ inst_lo,
+             int* __restrict__ inst_hi, long long* __restrict__ inst_upd) {
   __shared__ int sh[2][16];
+  __shared__ long long shc[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long k = st->rs.k;
   for (int c = blockIdx.x; c * kChunk < Btot; c += gridDim.x) {
     const int b = c * kChunk + threadIdx.x;
     int cols = 0, items = 0;
+    long long cost = 0;
     if (b < Btot) {
       const int q = blk_inst[b];
+      if (b == inst[q].blk_off) {  // every instance's first block resets its item range
+        inst_lo[q] = 0x7fffffff;
+        inst_hi[q] = -1;
+      }
       if (active[q] &&
           block_drawn((uint32_t)(b - inst[q].blk_off), (uint64_t)k, inst[q].inst_id, seed, T)) {
         cols = blk_len[b];
         items = (cols + kBC - 1) / kBC;
+        cost = (long long)cols * (inst[q].m + kBFColCost);
         atomicAdd((unsigned long long*)&inst_upd[q], (unsigned long long)cols);
       }
       blk_cols[b] = cols;
     }
     const int wc = wave_sum(cols), wi = wave_sum(items);
+    const long long wk = wave_sum_i64(cost);
     if (lane == 0) {
       sh[0][wave] = wc;
       sh[1][wave] = wi;
+      shc[wave] = wk;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       int a = 0, i = 0;
+      long long cc = 0;
       for (int w = 0; w < 16; ++w) {
         a += sh[0][w];
         i += sh[1][w];
+        cc += shc[w];
       }
       chunk_cols[c] = a;
       chunk_items[c] = i;
+      chunk_cost[c] = cc;
     }
     __syncthreads();
   }
 }
 
+// Exclusive scan of 64-bit values over a 1024-thread block; 'sh' needs 17 entries.
+__device__ __forceinline__ long long block_exclusive_scan_1024_i64(long long v, long long* sh,
+                                                                   long long* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long long inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long run = 0;
+    for (int w = 0; w < 16; ++w) {
+      const long long t = sh[w];
+      sh[w] = run;
+      run += t;
+    }
+    sh[16] = run;
+  }
+  __syncthreads();
+  const long long res = sh[wave] + inc - v;
+  *total = sh[16];
+  __syncthreads();
+  return res;
+}
+
+// Ordered lists of the round: drawn columns and work items (<= kBC columns of one block).
+// For the fused round (G > 0) also the cost prefix of every item, the first item of every
+// workgroup's share -- workgroup w takes the items whose cost prefix p satisfies
+// floor(p G / T) = w (T = the round's total cost), i.e. wg_first[w] is the first item with
+// p >= ceil(w T / G) -- and each instance's first and last item.
 __global__ void __launch_bounds__(1024)
 k_bsel_scatter(int Btot, const int* __restrict__ blk_inst, const int* __restrict__ blk_col0,
                const int* __restrict__ blk_cols, const int* __restrict__ chunk_cols,
-               const int* __restrict__ chunk_items, BState* __restrict__ st,
-               int* __restrict__ sel_cols, BItem* __restrict__ items) {
+               const int* __restrict__ chunk_items, const long long* __restrict__ chunk_cost,
+               const BInst* __restrict__ inst, BState* __restrict__ st,
+               int* __restrict__ sel_cols, BItem* __restrict__ items,
+               long long* __restrict__ item_pref, int* __restrict__ wg_first, int G,
+               int* __restrict__ inst_lo, int* __restrict__ inst_hi) {
   __shared__ int sh[17];
+  __shared__ long long shl[17];
   __shared__ int s_base[2];
+  __shared__ long long s_cbase[2];
   const int nch = (Btot + kChunk - 1) / kChunk;
   for (int c = blockIdx.x; c < nch; c += gridDim.x) {
     int pc = 0, pi = 0;
-    for (int q = threadIdx.x; q < c; q += 1024) {
-      pc += chunk_cols[q];
-      pi += chunk_items[q];
+    long long pk = 0, pall = 0;
+    for (int q = threadIdx.x; q < nch; q += 1024) {
+      if (q < c) {
+        pc += chunk_cols[q];
+        pi += chunk_items[q];
+        pk += chunk_cost[q];
+      }
+      pall += chunk_cost[q];
     }
     int tc, ti;
+    long long tk, tall;
     (void)block_exclusive_scan_1024(pc, sh, &tc);
     (void)block_exclusive_scan_1024(pi, sh, &ti);
+    (void)block_exclusive_scan_1024_i64(pk, shl, &tk);
+    (void)block_exclusive_scan_1024_i64(pall, shl, &tall);
     if (threadIdx.x == 0) {
       s_base[0] = tc;
       s_base[1] = ti;
+      s_cbase[0] = tk;
+      s_cbase[1] = tall;
     }
     __syncthreads();
+    const long long Tc = s_cbase[1];
     const int b = c * kChunk + threadIdx.x;
     const int cols = b < Btot ? blk_cols[b] : 0;
     const int nit = (cols + kBC - 1) / kBC;
+    const int q = b < Btot ? blk_inst[b] : 0;
+    const long long per = cols ? (long long)(inst[q].m + kBFColCost) : 0;
     int totc, toti;
+    long long totk;
     const int oc = s_base[0] + block_exclusive_scan_1024(cols, sh, &totc);
     const int oi = s_base[1] + block_exclusive_scan_1024(nit, sh, &toti);
+    const long long ok = s_cbase[0] + block_exclusive_scan_1024_i64(cols * per, shl, &totk);
     if (cols) {
-      const int c0 = blk_col0[b], q = blk_inst[b];
+      const int c0 = blk_col0[b];
       for (int u = 0; u < cols; ++u) sel_cols[oc + u] = c0 + u;
       for (int u = 0; u < nit; ++u) {
         BItem it;
@@ -113,11 +183,25 @@ k_bsel_scatter(int Btot, const int* __restrict__ blk_inst, const int* __restrict
         it.cnt = min(kBC, cols - u * kBC);
         it.inst = q;
         items[oi + u] = it;
+        if (G > 0) {
+          const long long p = ok + (long long)u * kBC * per;
+          const long long e = p + it.cnt * per;
+          item_pref[oi + u] = p;
+          // the workgroups whose share starts right after this item
+          const long long w0 = p * G / Tc + 1, w1 = e * G / Tc;
+          for (long long w = w0; w <= w1; ++w) wg_first[w] = oi + u + 1;
+          if (oi + u == 0) wg_first[0] = 0;
+        }
+      }
+      if (G > 0) {
+        atomicMin(&inst_lo[q], oi);
+        atomicMax(&inst_hi[q], oi + nit - 1);
       }
     }
     if (c == nch - 1 && threadIdx.x == 0) {
       st->rs.S_cnt = s_base[0] + totc;
       st->items = s_base[1] + toti;
+      st->cost = Tc;
     }
     __syncthreads();
   }
@@ -125,6 +209,7 @@ k_bsel_scatter(int Btot, const int* __restrict__ blk_inst, const int* __restrict
     if (Btot == 0) {
       st->rs.S_cnt = 0;
       st->items = 0;
+      st->cost = 0;
     }
     st->rs.work_ctr = 0;
     st->rs.k += 1;
@@ -245,6 +330,253 @@ k_bgrad(const BInst* __restrict__ inst, const BItem* __restrict__ items,
       x_all[j] = xj + d;
       dx_sel[t] = d;
     }
+  }
+}
+
+// ------------------------------------------------------------------ fused round
+// S.2-S.5 of every drawn column of every instance in one pass: a 512-thread workgroup holds
+// a group of columns of one instance in registers -- thread t owns the 16-byte row groups
+// t, t + 512, ..., t + (Q-1)*512 of each, Q = the instance's row groups per thread (1, 2 or
+// 4), C = 4/Q columns per group, so a group is 64 bytes per thread whatever m -- with
+// the same rows of the instance's r and of its own fold partial.  Workgroup w takes a
+// contiguous share of the round's items (the shares are cut by cost, rows plus a fixed part
+// per column, see k_bsel_scatter), so every partial sum has a fixed order.  When its share
+// moves on to the next instance, the workgroup writes its partial: straight into r when it
+// held all of that instance's items this round, otherwise into slot (w + k) for
+// k_bfused_reduce.  Row groups beyond an instance's m are clamped to its last one and their
+// values masked (A's padding rows may hold anything).  Registers are kept to 128 per thread
+// so that two workgroups share a compute unit: their groups in flight hide each other's
+// load latency (one workgroup with a prefetched second group measured slower).
+constexpr int kBFThreads = 512;
+constexpr int kBFWaves = kBFThreads / 64;
+constexpr int kBFMaxQ = 4;        // FP32 m <= 8192, FP64 m <= 4096
+constexpr int kBFMaxWgPerCu = 4;  // the partial slots are allocated for this many
+constexpr int kBFSlots = 4;       // 16-byte registers per thread and group (C * Q)
+
+__device__ __forceinline__ int bf_wg_of(long long pref, long long Tc, int G) {
+  return (int)min((long long)(G - 1), pref * G / Tc);
+}
+
+// Row groups per thread for an instance of nq 16-byte row groups.
+__device__ __forceinline__ int bf_q_of(int nq) {
+  return nq <= kBFThreads ? 1 : nq <= 2 * kBFThreads ? 2 : 4;
+}
+
+// One group of C = kBFSlots / Q consecutive columns j0 .. j0+cnt-1 of instance I: the
+// columns' row groups (masked past m), the C dot products with r (wave sums, then the 8
+// wave sums in a fixed order), the best responses and moves (threads c < cnt, broadcast
+// through LDS) and the fold into this thread's rows of the partial.
+template <typename T, int Q>
+__device__ __forceinline__ void bf_group(const BInst& I, int nq, int j0, int cnt,
+                                         typename V16<T>::v (&rr)[kBFMaxQ],
+                                         typename V16<T>::v (&pa)[kBFMaxQ],
+                                         const int (&nv)[kBFMaxQ], T (*red)[kBFWaves],
+                                         T* s_d,
+                                         int lane, int wave, int tid, T gamma,
+                                         const BRParams& bp, T* __restrict__ x_all,
+                                         const double* __restrict__ cn2, long long& moved) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  constexpr int C = kBFSlots / Q;
+  const char* A = reinterpret_cast<const char*>(I.A);
+  // the best-response inputs of column tid (threads < cnt) are loaded with the column
+  T xj = (T)0;
+  double q2 = 0.0;
+  if (tid < cnt) {
+    xj = x_all[j0 + tid];
+    q2 = cn2[j0 + tid];
+  }
+  VA a[C][Q];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const char* col = A + (size_t)(j0 + min(c, cnt - 1) - I.col_off) * I.lda * sizeof(T);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int gi = min(q * kBFThreads + tid, nq - 1);
+      a[c][q] = __builtin_nontemporal_load(reinterpret_cast<const VA*>(col + (size_t)gi * 16));
+    }
+  }
+  T acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < VN; ++e) a[c][q][e] = e < nv[q] ? a[c][q][e] : (T)0;
+    acc[c] = (T)0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < VN; ++e) acc[c] += a[c][q][e] * rr[q][e];
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const T v = wave_sum(acc[c]);
+    if (lane == 0) red[c][wave] = v;
+  }
+  __syncthreads();
+  if (tid < cnt) {
+    const T* rs = red[tid];
+    const T dot = ((rs[0] + rs[1]) + (rs[2] + rs[3])) + ((rs[4] + rs[5]) + (rs[6] + rs[7]));
+    T g = dot - (T)bp.c2 * xj;
+    if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+    const T qq = (T)(q2 + I.tau);
+    const T xh = soft_clip<T>(xj - g / qq, (T)bp.lam_eta / qq, (T)bp.beta);
+    const T d = gamma * (xh - xj);
+    x_all[j0 + tid] = xj + d;
+    s_d[tid] = d;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const T d = c < cnt ? s_d[c] : (T)0;
+    if (d != (T)0) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int e = 0; e < VN; ++e) pa[q][e] += a[c][q][e] * d;
+      if (tid == 0) ++moved;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBFThreads, 4)  // 4 waves per SIMD: two workgroups per CU
+k_bfused(const BInst* __restrict__ inst, const BItem* __restrict__ items,
+         const long long* __restrict__ item_pref, const int* __restrict__ wg_first,
+         const int* __restrict__ inst_lo, const int* __restrict__ inst_hi,
+         const int* __restrict__ sel_cols, T* __restrict__ r_all, T* __restrict__ x_all,
+         const double* __restrict__ cn2, BState* __restrict__ st, T* __restrict__ part,
+         long long pst, BRParams bp0) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  __shared__ T red[kBFSlots][kBFWaves];
+  __shared__ T s_d[kBFSlots];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int G = gridDim.x, w = blockIdx.x;
+  if (st->items == 0) return;
+  const long long Tc = st->cost;
+  const T gamma = (T)st->rs.gamma_cur;
+  const int i0 = wg_first[w], i1 = wg_first[w + 1];
+  if (i0 >= i1) return;
+  VA rr[kBFMaxQ], pa[kBFMaxQ];
+  int nv[kBFMaxQ];
+  int kcur = -1, qcur = 0;
+  long long moved = 0;
+  auto flush = [&]() {
+    const BInst& I = inst[kcur];
+    const int nq = (I.m + VN - 1) / VN;
+    const int lo = inst_lo[kcur], hi = inst_hi[kcur];
+    const bool whole = bf_wg_of(item_pref[lo], Tc, G) == w && bf_wg_of(item_pref[hi], Tc, G) == w;
+    T* dst = whole ? r_all + I.row_off : part + (size_t)(w + kcur) * pst;
+#pragma unroll
+    for (int q = 0; q < kBFMaxQ; ++q) {
+      const int gi = q * kBFThreads + tid;
+      if (q < qcur && gi < nq) {
+        VA v = pa[q];
+        if (whole) v += rr[q];
+        *reinterpret_cast<VA*>(dst + (size_t)gi * VN) = v;
+      }
+    }
+  };
+  for (int i = i0; i < i1; ++i) {
+    const BItem it = items[i];
+    const BInst& I = inst[it.inst];
+    const int nq = (I.m + VN - 1) / VN;
+    const int qk = bf_q_of(nq);
+    if (it.inst != kcur) {
+      if (kcur >= 0) flush();
+      kcur = it.inst;
+      qcur = qk;
+      const T* r = r_all + I.row_off;
+#pragma unroll
+      for (int q = 0; q < kBFMaxQ; ++q) {
+        const int g = q * kBFThreads + tid;
+        nv[q] = q < qk ? max(0, min(VN, I.m - g * VN)) : 0;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          rr[q][e] = (T)0;
+          pa[q][e] = (T)0;
+        }
+        if (q < qk) {
+          const VA v = *reinterpret_cast<const VA*>(r + (size_t)min(g, nq - 1) * VN);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) rr[q][e] = e < nv[q] ? v[e] : (T)0;
+        }
+      }
+    }
+    BRParams bp = bp0;
+    bp.lam = I.lam;
+    bp.lam_eta = I.lam * bp0.eta;
+    bp.c2 = 2.0 * I.c;
+    bp.beta = I.beta;
+    const int j00 = sel_cols[it.pos];
+    const int C = kBFSlots / qk;
+    for (int cs = 0; cs < it.cnt; cs += C) {
+      const int cnt = min(C, it.cnt - cs);
+      switch (qk) {
+        case 1:
+          bf_group<T, 1>(I, nq, j00 + cs, cnt, rr, pa, nv, red, s_d, lane, wave, tid, gamma, bp,
+                         x_all, cn2, moved);
+          break;
+        case 2:
+          bf_group<T, 2>(I, nq, j00 + cs, cnt, rr, pa, nv, red, s_d, lane, wave, tid, gamma, bp,
+                         x_all, cn2, moved);
+          break;
+        default:
+          bf_group<T, 4>(I, nq, j00 + cs, cnt, rr, pa, nv, red, s_d, lane, wave, tid, gamma, bp,
+                         x_all, cn2, moved);
+          break;
+      }
+    }
+  }
+  if (kcur >= 0) flush();
+  if (tid == 0 && moved)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&st->rs.moved_updates),
+              (unsigned long long)moved);
+}
+
+// r_k += the partial slots (w + k), w = the workgroups that shared instance k's items, in
+// workgroup order (instances held by one workgroup were written by it).  A workgroup whose
+// share is empty (an item costing more than a share spans several thresholds) wrote no
+// slot and is skipped.  One thread per row group; tile_base[k] = first tile (256 row
+// groups) of instance k.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bfused_reduce(int K, const BInst* __restrict__ inst, const int* __restrict__ tile_base,
+                const long long* __restrict__ item_pref, const int* __restrict__ wg_first,
+                const int* __restrict__ inst_lo, const int* __restrict__ inst_hi,
+                const BState* __restrict__ st, int G, const T* __restrict__ part, long long pst,
+                T* __restrict__ r_all) {
+  typedef typename V16<T>::v VA;
+  constexpr int VN = V16<T>::N;
+  const int ntiles = tile_base[K];
+  if (st->items == 0) return;
+  const long long Tc = st->cost;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int lo = 0, hi = K - 1;  // instance of the tile: last k with tile_base[k] <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_base[mid] <= tile)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int k = lo;
+    const int ilo = inst_lo[k], ihi = inst_hi[k];
+    if (ilo > ihi) continue;
+    const int w0 = bf_wg_of(item_pref[ilo], Tc, G), w1 = bf_wg_of(item_pref[ihi], Tc, G);
+    if (w0 == w1) continue;
+    const BInst& I = inst[k];
+    const int nq = (I.m + VN - 1) / VN;
+    const int gi = (tile - tile_base[k]) * 256 + threadIdx.x;
+    if (gi >= nq) continue;
+    T* r = r_all + I.row_off + (size_t)gi * VN;
+    VA s = *reinterpret_cast<const VA*>(r);
+    for (int ww = w0; ww <= w1; ++ww)
+      if (wg_first[ww] < wg_first[ww + 1])
+        s += *reinterpret_cast<const VA*>(part + (size_t)(ww + k) * pst + (size_t)gi * VN);
+    *reinterpret_cast<VA*>(r) = s;
   }
 }
 
@@ -387,19 +719,29 @@ k_bfold_reduce(const TB* __restrict__ base, double base_scale, const Acc* __rest
 }
 
 // ------------------------------------------------------------------ checks
-// One workgroup per instance: F_k from the FP64 residual, then the stopping test.
-template <typename T>
+// One workgroup per instance: F_k (FP64 accumulation) from the residual rsrc, then the
+// stopping test of the relative objective error.
+//  mode 0: rsrc is a fresh FP64 residual; an active instance below the tolerance stops.
+//  mode 1: rsrc is the running residual; an active instance below the tolerance becomes a
+//          candidate (cand[k] = 1), to be confirmed with a fresh residual.
+//  mode 2: rsrc is a fresh FP64 residual of the candidates; a candidate below the tolerance
+//          stops, any other restarts its running residual rrun from the fresh one.
+// A non-finite F stops the instance in every mode.
+template <typename T, typename TR>
 __global__ void __launch_bounds__(256)
-k_bobj_check(int K, const BInst* __restrict__ inst, const double* __restrict__ r64,
+k_bobj_check(int K, const BInst* __restrict__ inst, const TR* __restrict__ rsrc,
              const T* __restrict__ x_all, BRParams bp0, double tol, const BState* __restrict__ st,
-             double* __restrict__ Fk, int* __restrict__ active, long long* __restrict__ done_round) {
+             double* __restrict__ Fk, int* __restrict__ active, long long* __restrict__ done_round,
+             int mode, int* __restrict__ cand, T* __restrict__ rrun) {
   __shared__ double res[3];
+  __shared__ int s_restart;
   for (int k = blockIdx.x; k < K; k += gridDim.x) {
+    if (mode == 2 && !cand[k]) continue;  // uniform over the workgroup
     const BInst& I = inst[k];
     BRParams bp = bp0;
     double sr = 0.0, sx = 0.0, sh = 0.0;
     for (int i = threadIdx.x; i < I.m; i += 256) {
-      const double v = r64[I.row_off + i];
+      const double v = (double)rsrc[I.row_off + i];
       sr += v * v;
     }
     for (int j = threadIdx.x; j < I.n; j += 256) {
@@ -412,17 +754,35 @@ k_bobj_check(int K, const BInst* __restrict__ inst, const double* __restrict__ r
     if (threadIdx.x == 0) {
       const double F = 0.5 * res[0] - I.c * res[1] + I.lam * res[2];
       Fk[k] = F;
+      s_restart = 0;
+      const bool below = tol > 0.0 && I.F_star != 0.0 && (F - I.F_star) / fabs(I.F_star) <= tol;
+      if (mode == 1) cand[k] = active[k] && below && isfinite(F);
       if (active[k]) {
-        bool stop = !isfinite(F);
-        if (tol > 0.0 && I.F_star != 0.0 && (F - I.F_star) / fabs(I.F_star) <= tol) stop = true;
+        const bool stop = !isfinite(F) || (mode != 1 && below);
         if (stop) {
           active[k] = 0;
           done_round[k] = st->rs.k;
+        } else if (mode == 2) {
+          s_restart = 1;
         }
       }
+      if (mode == 2) cand[k] = 0;
     }
     __syncthreads();
+    if (s_restart)
+      for (int i = threadIdx.x; i < I.m; i += 256) rrun[I.row_off + i] = (T)rsrc[I.row_off + i];
+    __syncthreads();
   }
+}
+
+// v[j] = x[j] for the columns of candidate instances, 0 elsewhere (the fresh residual of the
+// confirmation is then folded from the candidates' columns only).
+template <typename T>
+__global__ void k_bmask_cand(const T* __restrict__ x_all, const int* __restrict__ col_inst,
+                             const int* __restrict__ cand, long long Ntot, T* __restrict__ v) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < Ntot;
+       j += (long long)gridDim.x * blockDim.x)
+    v[j] = cand[col_inst[j]] ? x_all[j] : (T)0;
 }
 
 template <typename T>
@@ -551,7 +911,9 @@ void batch_free(sca_batch* B) {
                   B->d_cn2, B->d_b, B->d_r64, B->d_rrun, B->d_sel_cols, B->d_items,
                   B->d_dx_sel, B->d_J_idx, B->d_J_val, B->d_J_lo, B->d_Jn, B->d_G, B->d_ng, B->d_nrt,
                   B->d_tile_off, B->d_part, B->d_state, B->d_active, B->d_done, B->d_upd,
-                  B->d_F, B->d_cm, B->d_cs, B->d_cz, B->d_pr};
+                  B->d_F, B->d_cm, B->d_cs, B->d_cz, B->d_pr, B->d_item_pref,
+                  B->d_chunk_cost, B->d_wg_first, B->d_inst_lo, B->d_inst_hi,
+                  B->d_tile_base, B->d_bpart, B->d_cand};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (B->graph) (void)hipGraphExecDestroy(B->graph);
@@ -593,6 +955,18 @@ void batch_compact(sca_batch* B, const T* v, const int* idx, const int* N_ptr, l
                      (RoundState*)B->d_state, count_moved);
 }
 
+int bf_grid(const sca_batch* B) { return B->bf_wg_per_cu * B->ncu; }
+
+template <typename T>
+void launch_bfused(sca_batch* B, T* x, T* r, const BRParams& bp, hipStream_t s) {
+  hipLaunchKernelGGL((k_bfused<T>), dim3(bf_grid(B)), dim3(kBFThreads), 0, s,
+                     (const BInst*)B->d_inst, (const BItem*)B->d_items,
+                     (const long long*)B->d_item_pref, (const int*)B->d_wg_first,
+                     (const int*)B->d_inst_lo, (const int*)B->d_inst_hi,
+                     (const int*)B->d_sel_cols, r, x, (const double*)B->d_cn2, B->d_state,
+                     (T*)B->d_bpart, B->bf_pst, bp);
+}
+
 template <typename T>
 void batch_round(sca_batch* B, const sca_opts* o, T* x, T* r, hipStream_t s) {
   const uint64_t Tthr = selection_threshold(o->select_p);
@@ -605,16 +979,30 @@ void batch_round(sca_batch* B, const sca_opts* o, T* x, T* r, hipStream_t s) {
   bp.theta = B->theta;
   bp.eta = B->eta;
   bp.reg = B->reg;
+  const bool fused = B->bf_kind == 1 && B->bf_q > 0;
+  const int G = fused ? bf_grid(B) : 0;
   const int nch = (B->Btot + kChunk - 1) / kChunk;
   const int cg = std::max(1, std::min(nch, 2 * B->ncu));
   hipLaunchKernelGGL(k_bsel_count, dim3(cg), dim3(1024), 0, s, B->Btot, (const int*)B->d_blk_inst,
                      (const int*)B->d_blk_len, (const BInst*)B->d_inst, (const int*)B->d_active,
                      o->seed, Tthr, (const BState*)B->d_state, B->d_blk_cols, B->d_chunk_a,
-                     B->d_chunk_b, B->d_upd);
+                     B->d_chunk_b, B->d_chunk_cost, B->d_inst_lo, B->d_inst_hi, B->d_upd);
   hipLaunchKernelGGL(k_bsel_scatter, dim3(cg), dim3(1024), 0, s, B->Btot,
                      (const int*)B->d_blk_inst, (const int*)B->d_blk_col0,
                      (const int*)B->d_blk_cols, (const int*)B->d_chunk_a,
-                     (const int*)B->d_chunk_b, B->d_state, B->d_sel_cols, B->d_items);
+                     (const int*)B->d_chunk_b, (const long long*)B->d_chunk_cost,
+                     (const BInst*)B->d_inst, B->d_state, B->d_sel_cols, B->d_items,
+                     B->d_item_pref, B->d_wg_first, G, B->d_inst_lo, B->d_inst_hi);
+  if (fused) {
+    launch_bfused<T>(B, x, r, bp, s);
+    const int g = std::max(1, std::min(B->bf_tiles, 16 * B->ncu));
+    hipLaunchKernelGGL((k_bfused_reduce<T>), dim3(g), dim3(256), 0, s, B->K,
+                       (const BInst*)B->d_inst, (const int*)B->d_tile_base,
+                       (const long long*)B->d_item_pref, (const int*)B->d_wg_first,
+                       (const int*)B->d_inst_lo, (const int*)B->d_inst_hi,
+                       (const BState*)B->d_state, G, (const T*)B->d_bpart, B->bf_pst, r);
+    return;
+  }
   hipLaunchKernelGGL((k_bgrad<T, 2>), dim3(2 * B->ncu), dim3(256), 0, s, (const BInst*)B->d_inst,
                      (const BItem*)B->d_items, (const int*)B->d_sel_cols, (const T*)r, x,
                      (const double*)B->d_cn2, B->d_state, (T*)B->d_dx_sel, bp);
@@ -644,9 +1032,30 @@ BRParams batch_brparams(const sca_batch* B) {
 
 template <typename T>
 void batch_check(sca_batch* B, const T* x, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_bobj_check<T>, dim3(std::min(B->K, 4 * B->ncu)), dim3(256), 0, s, B->K,
+  hipLaunchKernelGGL((k_bobj_check<T, double>), dim3(std::min(B->K, 4 * B->ncu)), dim3(256), 0,
+                     s, B->K, (const BInst*)B->d_inst, (const double*)B->d_r64, x,
+                     batch_brparams(B), tol, (const BState*)B->d_state, B->d_F, B->d_active,
+                     B->d_done, 0, B->d_cand, (T*)nullptr);
+}
+
+// The relative-error test of sca_batch_solve from the running residual r; the instances
+// below the tolerance are confirmed with a fresh FP64 residual folded from their own
+// columns only (a failed confirmation restarts their running residual from it).
+template <typename T>
+void batch_check_running(sca_batch* B, const T* x, T* r, double tol, hipStream_t s) {
+  const int gk = std::min(B->K, 4 * B->ncu);
+  hipLaunchKernelGGL((k_bobj_check<T, T>), dim3(gk), dim3(256), 0, s, B->K,
+                     (const BInst*)B->d_inst, (const T*)r, x, batch_brparams(B), tol,
+                     (const BState*)B->d_state, B->d_F, B->d_active, B->d_done, 1, B->d_cand, r);
+  const int g = (int)std::min<long long>((B->Ntot + 255) / 256, 16ll * B->ncu);
+  hipLaunchKernelGGL(k_bmask_cand<T>, dim3(g), dim3(256), 0, s, x, (const int*)B->d_col_inst,
+                     (const int*)B->d_cand, B->Ntot, (T*)B->d_dx_sel);
+  batch_compact<T>(B, (const T*)B->d_dx_sel, (const int*)nullptr, (const int*)N_total_ptr(B),
+                   B->Ntot, 0, s);
+  batch_fold<T, double, T, T>(B, (const T*)B->d_b, -1.0, (T*)nullptr, B->d_r64, s);
+  hipLaunchKernelGGL((k_bobj_check<T, double>), dim3(gk), dim3(256), 0, s, B->K,
                      (const BInst*)B->d_inst, (const double*)B->d_r64, x, batch_brparams(B), tol,
-                     (const BState*)B->d_state, B->d_F, B->d_active, B->d_done);
+                     (const BState*)B->d_state, B->d_F, B->d_active, B->d_done, 2, B->d_cand, r);
 }
 
 template <typename T>
@@ -807,6 +1216,26 @@ extern "C" sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t
   BALLOC(B->d_cs, sizeof(double) * Ntot);
   BALLOC(B->d_cz, sizeof(int) * Ntot);
   BALLOC(B->d_pr, sizeof(double) * 3 * count);
+  // fused round: where every instance's column fits the registers of a 256-thread workgroup
+  {
+    const long long VN = 16 / (long long)es;
+    long long mmax = 0;
+    for (int64_t k = 0; k < count; ++k) mmax = std::max<long long>(mmax, items[k].m);
+    const long long nq = (mmax + VN - 1) / VN;
+    const long long q = (nq + kBFThreads - 1) / kBFThreads;
+    B->bf_q = q <= 1 ? 1 : q <= 2 ? 2 : q <= kBFMaxQ ? 4 : 0;
+    B->bf_pst = (mmax + VN - 1) / VN * VN;
+    B->bf_gmax = kBFMaxWgPerCu * B->ncu;
+  }
+  BALLOC(B->d_item_pref, sizeof(long long) * (Ntot + 1));
+  BALLOC(B->d_chunk_cost, sizeof(long long) * nchB);
+  BALLOC(B->d_wg_first, sizeof(int) * (B->bf_gmax + 1));
+  BALLOC(B->d_inst_lo, sizeof(int) * count);
+  BALLOC(B->d_inst_hi, sizeof(int) * count);
+  BALLOC(B->d_tile_base, sizeof(int) * (count + 1));
+  BALLOC(B->d_cand, sizeof(int) * count);
+  if (B->bf_q > 0)
+    BALLOC(B->d_bpart, es * (size_t)B->bf_pst * (B->bf_gmax + count));
 #undef BALLOC
   if (st == SCA_OK) {
     bool ok = hipMemcpy(B->d_inst, B->hinst.data(), sizeof(BInst) * count,
@@ -821,11 +1250,21 @@ extern "C" sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t
                         hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(B->d_col_inst, col_inst.data(), sizeof(int) * Ntot,
                         hipMemcpyHostToDevice) == hipSuccess;
+    std::vector<int> tb(count + 1, 0);
+    const long long VN = 16 / (long long)es;
+    for (int64_t k = 0; k < count; ++k) {
+      const long long nq = (items[k].m + VN - 1) / VN;
+      tb[k + 1] = tb[k] + (int)((nq + 255) / 256);
+    }
+    B->bf_tiles = tb[count];
+    ok = ok && hipMemcpy(B->d_tile_base, tb.data(), sizeof(int) * (count + 1),
+                         hipMemcpyHostToDevice) == hipSuccess;
     // padding rows of b, r and the fold partials stay zero
     ok = ok && hipMemsetAsync(B->d_b, 0, es * Mtot, s) == hipSuccess &&
          hipMemsetAsync(B->d_rrun, 0, es * Mtot + 16, s) == hipSuccess &&
          hipMemsetAsync(B->d_part, 0, sizeof(double) * kBMaxGroups * Mtot, s) == hipSuccess &&
-         hipMemsetAsync(B->d_r64, 0, sizeof(double) * Mtot, s) == hipSuccess;
+         hipMemsetAsync(B->d_r64, 0, sizeof(double) * Mtot, s) == hipSuccess &&
+         hipMemsetAsync(B->d_cand, 0, sizeof(int) * count, s) == hipSuccess;
     for (int64_t k = 0; ok && k < count; ++k)
       ok = hipMemcpyAsync((char*)B->d_b + es * B->roff[k], items[k].b_dev, es * items[k].m,
                           hipMemcpyDeviceToDevice, s) == hipSuccess;
@@ -859,6 +1298,17 @@ extern "C" sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t
       }
     }
   }
+  if (st == SCA_OK) {  // launch shape: the tuning table's batch row, else the default
+    sca_launch l;
+    long long mmax = 0;
+    for (int64_t k = 0; k < count; ++k) mmax = std::max<long long>(mmax, items[k].m);
+    if (batch_tuning(dtype, mmax, &l) && (l.grad_kind == 0 || B->bf_q > 0)) {
+      B->bf_kind = l.grad_kind;
+      if (l.grad_kind == 1) {
+        B->bf_wg_per_cu = l.grad_wg_per_cu;
+      }
+    }
+  }
   if (st == SCA_OK && hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
     st = set_error(SCA_EHIP, "stream creation failed");
   if (st != SCA_OK) {
@@ -874,6 +1324,41 @@ extern "C" void sca_batch_destroy(sca_batch* B) {
   if (!B) return;
   batch_free(B);
   delete B;
+}
+
+extern "C" sca_status sca_batch_get_launch(sca_batch* B, sca_launch* out) {
+  if (!B || !out) return set_error(SCA_EINVAL, "NULL argument");
+  out->struct_size = sizeof(sca_launch);
+  out->grad_kind = (B->bf_kind == 1 && B->bf_q > 0) ? 1 : 0;
+  out->grad_cols = kBFSlots;
+  out->grad_unroll = 1;
+  out->grad_wg_per_cu = B->bf_wg_per_cu;
+  return SCA_OK;
+}
+
+extern "C" sca_status sca_batch_set_launch(sca_batch* B, const sca_launch* l) {
+  if (!B || !l) return set_error(SCA_EINVAL, "NULL argument");
+  if (l->struct_size != sizeof(sca_launch)) return set_error(SCA_EINVAL, "struct_size mismatch");
+  if (l->grad_kind != 0 && l->grad_kind != 1)
+    return set_error(SCA_EINVAL, "batch grad_kind must be 0 (two-pass) or 1 (fused)");
+  if (l->grad_kind == 1) {
+    if (B->bf_q == 0)
+      return set_error(SCA_EINVAL, "the fused round needs every m <= %d (this dtype)",
+                       kBFThreads * kBFMaxQ * (int)(16 / B->esize));
+    if (l->grad_cols != kBFSlots)
+      return set_error(SCA_EINVAL, "fused batch round: grad_cols must be %d (16-byte registers "
+                       "per thread and group: columns x row groups)", kBFSlots);
+    if (l->grad_wg_per_cu < 1 || l->grad_wg_per_cu > kBFMaxWgPerCu)
+      return set_error(SCA_EINVAL, "fused batch round: grad_wg_per_cu must lie in [1, %d]",
+                       kBFMaxWgPerCu);
+    B->bf_wg_per_cu = l->grad_wg_per_cu;
+  }
+  B->bf_kind = l->grad_kind;
+  if (B->graph) {  // the cached solve graph holds the old launch shape
+    (void)hipGraphExecDestroy(B->graph);
+    B->graph = nullptr;
+  }
+  return SCA_OK;
 }
 
 extern "C" sca_status sca_batch_layout(sca_batch* B, int64_t* x_off, int64_t* r_off) {
@@ -968,14 +1453,19 @@ extern "C" sca_status sca_batch_objective(sca_batch* B, const sca_opts* o, const
   return SCA_OK;
 }
 
-// E rounds followed by a fresh FP64 residual and the per-instance stopping tests
-// (relative objective error, and the merit when tol_merit > 0).
+// E rounds followed by the per-instance stopping tests: the relative objective error from
+// the running residual, confirmed with a fresh one (as sca_solve does); with tol_merit > 0
+// a fresh FP64 residual of every instance for both tests and the merit.
 template <typename T>
 static void batch_cycle(sca_batch* B, const sca_opts* o, T* x, T* r, hipStream_t s) {
   for (int64_t i = 0; i < o->check_every; ++i) batch_round<T>(B, o, x, r, s);
-  batch_residual<T>(B, x, r, s);
+  if (o->tol_merit <= 0.0) {
+    batch_check_running<T>(B, x, r, o->tol_rel_obj, s);
+    return;
+  }
+  batch_residual<T>(B, x, (T*)nullptr, s);
   batch_check<T>(B, x, o->tol_rel_obj, s);
-  if (o->tol_merit > 0.0) {
+  {
     batch_probe<T>(B, x, s);
     hipLaunchKernelGGL(k_bmerit_check, dim3(std::max(1, (B->K + 255) / 256)), dim3(256), 0, s,
                        B->K, (const double*)B->d_pr, o->tol_merit, (const BState*)B->d_state,

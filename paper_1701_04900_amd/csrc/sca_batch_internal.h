@@ -28,10 +28,10 @@ struct BItem {
 };
 
 struct BState {
-  RoundState rs;  // round counter, step, totals, compaction results
-  int items;      // work items of the round in flight
-  int tiles;      // fold tiles of the fold in flight
-  int pad[2];
+  RoundState rs;   // round counter, step, totals, compaction results
+  int items;       // work items of the round in flight
+  int tiles;       // fold tiles of the fold in flight
+  long long cost;  // fused round: total cost of the round's items (the shares' split)
 };
 
 
@@ -80,6 +80,24 @@ struct sca_batch {
   double *d_cm = nullptr, *d_cs = nullptr;
   int* d_cz = nullptr;
   double* d_pr = nullptr;
+  // fused round (bf_q > 0): one pass over the drawn columns with the fold from registers;
+  // item cost prefix, first item of every workgroup's share, first/last item of every
+  // instance, chunk cost sums, one partial m-vector per (workgroup, instance) slot
+  int bf_wg_per_cu = 2;  // 256-thread workgroups per CU
+  int bf_kind = 1;       // 1: fused round, 0: two-pass round
+  int bf_q = 0;          // row groups per thread (template), 0 when the fused round cannot run
+  long long bf_pst = 0;  // partial slot stride (elements)
+  int bf_gmax = 0;       // largest grid the partial slots were allocated for
+  long long* d_item_pref = nullptr;
+  long long* d_chunk_cost = nullptr;
+  int* d_wg_first = nullptr;
+  int* d_inst_lo = nullptr;
+  int* d_inst_hi = nullptr;
+  int* d_tile_base = nullptr;
+  int bf_tiles = 0;
+  void* d_bpart = nullptr;
+  // checks of sca_batch_solve from the running residual (candidates confirmed fresh)
+  int* d_cand = nullptr;
   sca_adj_cache* adj = nullptr;
   hipStream_t cap = nullptr;
   hipGraphExec_t graph = nullptr;

@@ -116,6 +116,7 @@ uint64_t selection_threshold(double p);
 void prof_begin(sca_problem* p, hipStream_t s, int kind);
 void prof_end(sca_problem* p, hipStream_t s, double bytes);
 void apply_tuning(sca_problem* p);
+bool batch_tuning(int dtype, int64_t mmax, sca_launch* out);  // the batch row of the table
 void launch_select(sca_problem* p, const sca_opts* o, uint64_t Tthr, hipStream_t s);
 void init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begin, hipStream_t s);
 void residual_any(sca_problem* p, const void* x, void* r_out, hipStream_t s);

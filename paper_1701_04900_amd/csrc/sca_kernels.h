@@ -637,9 +637,15 @@ k_grad_br_wwalk(const T* __restrict__ A, long long lda, int m, const T* __restri
 // bytes of A instead), which keeps the compiler's wait counts exact.
 // part[w] receives workgroup w's partial (k_part_reduce adds them to r);
 // st->moved_updates counts the moved coordinates.
+// Longer columns (L > 0): beyond the Q row groups in registers, each thread keeps L more
+// row groups of the column, of r and of its partial in LDS slots that only it touches
+// (Q = the register limit, C = 1); the next column's LDS part is loaded into registers
+// with the rest of the next group and stored to the slots once the current column is done.
 constexpr int kFusedMaxQ32 = 5;  // row groups per thread (registers), FP32
 constexpr int kFusedMaxQ64 = 3;  // and FP64
+constexpr int kFusedMaxL = 3;    // row groups per thread in LDS (3 x 16 KB each for A, r, partial)
 constexpr int kFusedSelCols = 4096;     // LDS list of a workgroup's share (draw in the kernel)
+constexpr int kFusedSelColsL = 2048;    // the same with LDS row groups
 constexpr int kFusedSelBlocks = 32768;  // blocks drawn in the kernel (32 per thread at most)
 
 // Block draw of the fused round (on = 0: the drawn list comes from k_select).
@@ -660,7 +666,7 @@ struct FusedBuf {
   double q2[C];
 };
 
-template <typename T, int Q, int C>
+template <typename T, int Q, int C, int L = 0>
 __global__ void __launch_bounds__(1024)
 k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restrict__ r,
                T* __restrict__ x, const double* __restrict__ cn2,
@@ -668,20 +674,34 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
                T* __restrict__ part, long long ldp, BRParams bp, FusedSel fs) {
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
+  constexpr int LL = L > 0 ? L : 1;
+  static_assert(L == 0 || C == 1, "LDS row groups go with one column per group");
   __shared__ T red[2][C][16];
   __shared__ int s_scan[17];
-  __shared__ int s_cols[kFusedSelCols];
+  __shared__ int s_cols[L > 0 ? kFusedSelColsL : kFusedSelCols];
+  // thread-private LDS row groups: the current column, r, the partial
+  __shared__ VA s_ext[L > 0 ? 3 * L * 1024 : 1];
+  VA* s_a = s_ext;
+  VA* s_rr = s_ext + LL * 1024;
+  VA* s_pa = s_ext + 2 * LL * 1024;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = gridDim.x;
   const int nq = (m + VN - 1) / VN;  // row groups holding rows < m (lda covers them)
-  // Byte offsets of the owned row groups within a column.  The last slot is the only one
-  // that can reach past row m: it is clamped to the last row group, and its rows >= m are
-  // zeroed after each load (A's padding rows may hold anything).
-  uint32_t boff[Q];
+  // Byte offsets of the owned row groups within a column (register slots q < Q, then LDS
+  // slots Q + l).  The last slot is the only one that can reach past row m: it is clamped
+  // to the last row group, and its rows >= m are zeroed after each load (A's padding rows
+  // may hold anything).
+  constexpr int QL = Q + L;
+  uint32_t boff[Q], loff[LL];
 #pragma unroll
-  for (int q = 0; q < Q - 1; ++q) boff[q] = (uint32_t)((q * 1024 + tid) * 16);
-  boff[Q - 1] = (uint32_t)(min((Q - 1) * 1024 + tid, nq - 1) * 16);
-  const int rlast = ((Q - 1) * 1024 + tid) * VN;
+  for (int q = 0; q < Q; ++q) boff[q] = (uint32_t)((q * 1024 + tid) * 16);
+#pragma unroll
+  for (int l = 0; l < LL; ++l) loff[l] = (uint32_t)(((Q + l) * 1024 + tid) * 16);
+  if (L == 0)
+    boff[Q - 1] = (uint32_t)(min((Q - 1) * 1024 + tid, nq - 1) * 16);
+  else
+    loff[LL - 1] = (uint32_t)(min((QL - 1) * 1024 + tid, nq - 1) * 16);
+  const int rlast = ((QL - 1) * 1024 + tid) * VN;
   const int nlast = max(0, min(VN, m - rlast));  // valid rows of the last slot
   VA rr[Q], pa[Q];
 #pragma unroll
@@ -695,6 +715,23 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
     }
 #pragma unroll
     for (int e = 0; e < VN; ++e) pa[q][e] = (T)0;
+  }
+  if constexpr (L > 0) {
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int row = ((Q + l) * 1024 + tid) * VN;
+      VA v;
+      if (row + VN <= m) {
+        v = *reinterpret_cast<const VA*>(r + row);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) v[e] = row + e < m ? r[row + e] : (T)0;
+      }
+      s_rr[l * 1024 + tid] = v;
+#pragma unroll
+      for (int e = 0; e < VN; ++e) v[e] = (T)0;
+      s_pa[l * 1024 + tid] = v;
+    }
   }
   // S.1, here or in k_select.  Here (fs.on): every workgroup evaluates the draw of every
   // block (the k_select draw, round st->k), scans the drawn columns in block order and lists
@@ -736,6 +773,7 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
   const int t1 = (int)((long long)S * (blockIdx.x + 1) / G);
   const int nitems = (t1 - t0 + C - 1) / C;
   long long moved = 0;
+  VA aln[LL];  // the LDS part of the next column, staged in registers
   auto load = [&](int tb, FusedBuf<T, Q, C>& B) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -747,15 +785,35 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
       for (int q = 0; q < Q; ++q)
         B.a[c][q] = __builtin_nontemporal_load(
             reinterpret_cast<const VA*>(col + (boff[q] & omask)));
+      if constexpr (L > 0) {
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+          aln[l] = __builtin_nontemporal_load(
+              reinterpret_cast<const VA*>(col + (loff[l] & omask)));
+      }
       B.x[c] = x[B.j[c]];
       B.q2[c] = cn2[B.j[c]];
+    }
+  };
+  // the staged LDS part becomes the current column's (rows >= m zeroed)
+  auto stage = [&]() {
+    if constexpr (L > 0) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        VA v = aln[l];
+        if (l == L - 1 && nlast < VN) {
+#pragma unroll
+          for (int e = 0; e < VN; ++e) v[e] = e < nlast ? v[e] : (T)0;
+        }
+        s_a[l * 1024 + tid] = v;
+      }
     }
   };
   auto process = [&](int tb, FusedBuf<T, Q, C>& B, int buf) {
     T acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      if (nlast < VN) {
+      if (L == 0 && nlast < VN) {
 #pragma unroll
         for (int e = 0; e < VN; ++e) B.a[c][Q - 1][e] = e < nlast ? B.a[c][Q - 1][e] : (T)0;
       }
@@ -764,6 +822,14 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
       for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int e = 0; e < VN; ++e) acc[c] += B.a[c][q][e] * rr[q][e];
+      if constexpr (L > 0) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          const VA av = s_a[l * 1024 + tid], rv = s_rr[l * 1024 + tid];
+#pragma unroll
+          for (int e = 0; e < VN; ++e) acc[c] += av[e] * rv[e];
+        }
+      }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -789,6 +855,16 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
           for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int e = 0; e < VN; ++e) pa[q][e] += B.a[c][q][e] * d;
+          if constexpr (L > 0) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+              const VA av = s_a[l * 1024 + tid];
+              VA pv = s_pa[l * 1024 + tid];
+#pragma unroll
+              for (int e = 0; e < VN; ++e) pv[e] += av[e] * d;
+              s_pa[l * 1024 + tid] = pv;
+            }
+          }
           ++moved;
         }
         if (tid == 0) x[B.j[c]] = xj + d;
@@ -798,17 +874,30 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
   if (nitems > 0) {
     FusedBuf<T, Q, C> B0, B1;
     load(t0, B0);
+    stage();
     for (int it = 0; it < nitems; ++it) {
       load(t0 + (it + 1) * C, B1);
       process(t0 + it * C, B0, it & 1);
       B0 = B1;
+      stage();
     }
   }
   T* dst = part + (size_t)blockIdx.x * ldp;
+  if constexpr (L == 0) {
 #pragma unroll
-  for (int q = 0; q < Q - 1; ++q)
-    *reinterpret_cast<VA*>(dst + (q * 1024 + tid) * VN) = pa[q];
-  if ((Q - 1) * 1024 + tid < nq) *reinterpret_cast<VA*>(dst + rlast) = pa[Q - 1];
+    for (int q = 0; q < Q - 1; ++q)
+      *reinterpret_cast<VA*>(dst + (q * 1024 + tid) * VN) = pa[q];
+    if ((Q - 1) * 1024 + tid < nq) *reinterpret_cast<VA*>(dst + rlast) = pa[Q - 1];
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      *reinterpret_cast<VA*>(dst + (q * 1024 + tid) * VN) = pa[q];
+#pragma unroll
+    for (int l = 0; l < L - 1; ++l)
+      *reinterpret_cast<VA*>(dst + ((Q + l) * 1024 + tid) * VN) = s_pa[l * 1024 + tid];
+    if ((QL - 1) * 1024 + tid < nq)
+      *reinterpret_cast<VA*>(dst + rlast) = s_pa[(L - 1) * 1024 + tid];
+  }
   if (tid == 0) {
     if (moved) atomicAdd(reinterpret_cast<unsigned long long*>(&st->moved_updates),
                          (unsigned long long)moved);

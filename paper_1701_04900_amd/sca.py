@@ -70,7 +70,7 @@ class sca_launch(ctypes.Structure):
 
 
 class sca_tune_entry(ctypes.Structure):
-    _fields_ = [("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32), ("m_lo", ctypes.c_int64),
+    _fields_ = [("dtype", ctypes.c_int32), ("target", ctypes.c_int32), ("m_lo", ctypes.c_int64),
                 ("m_hi", ctypes.c_int64), ("launch", sca_launch)]
 
 
@@ -110,6 +110,8 @@ SIGNATURES = {
     "sca_batch_create": (_S, [ctypes.POINTER(_P), _S, _I64, ctypes.POINTER(sca_batch_item), _P]),
     "sca_batch_destroy": (None, [_P]),
     "sca_batch_layout": (_S, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "sca_batch_get_launch": (_S, [_P, ctypes.POINTER(sca_launch)]),
+    "sca_batch_set_launch": (_S, [_P, ctypes.POINTER(sca_launch)]),
     "sca_batch_set_regularizer": (_S, [_P, _S, _D]),
     "sca_batch_set_fstar": (_S, [_P, ctypes.POINTER(_D)]),
     "sca_batch_residual": (_S, [_P, _P, _P, _P]),
@@ -240,7 +242,8 @@ def load_tuning(path=None):
     rows = json.load(open(path))["entries"]
     arr = (sca_tune_entry * len(rows))()
     for i, e in enumerate(rows):
-        arr[i] = sca_tune_entry(SCA_F32 if e["dtype"] == "f32" else SCA_F64, 0, e["m_lo"], e["m_hi"],
+        arr[i] = sca_tune_entry(SCA_F32 if e["dtype"] == "f32" else SCA_F64,
+                                1 if e.get("target") == "batch" else 0, e["m_lo"], e["m_hi"],
                                 sca_launch(ctypes.sizeof(sca_launch), e["grad_kind"],
                                            e["grad_cols"], e["grad_unroll"], e["grad_wg_per_cu"]))
     _check(_LIB.sca_tuning_set(arr, len(rows)))
@@ -484,6 +487,18 @@ def sca_batch_layout(h, K):
     ro = (_I64 * (K + 1))()
     _check(lib().sca_batch_layout(h, xo, ro))
     return np.array(xo[:], dtype=np.int64), np.array(ro[:], dtype=np.int64)
+
+
+def sca_batch_get_launch(h):
+    out = sca_launch()
+    _check(lib().sca_batch_get_launch(h, ctypes.byref(out)))
+    return dict(grad_kind=out.grad_kind, grad_cols=out.grad_cols, grad_unroll=out.grad_unroll,
+                grad_wg_per_cu=out.grad_wg_per_cu)
+
+
+def sca_batch_set_launch(h, grad_kind, grad_cols=4, grad_wg_per_cu=2):
+    l = sca_launch(ctypes.sizeof(sca_launch), grad_kind, grad_cols, 1, grad_wg_per_cu)
+    _check(lib().sca_batch_set_launch(h, ctypes.byref(l)))
 
 
 def sca_batch_set_regularizer(h, reg, theta=0.0):

@@ -100,3 +100,24 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=300)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_tuning_table_rows_are_validated(L):
+    """The committed table installs; a batch row (target 1) takes only the batch shapes and a
+    single-problem row (target 0) only the single-problem ones (host-side checks)."""
+    import json
+    rows = json.load(open(sca.TUNING_PATH))["entries"]
+    assert sca.load_tuning() == len(rows)
+    size = ctypes.sizeof(sca.sca_launch)
+    good = [sca.sca_tune_entry(sca.SCA_F32, 1, 1, 8192, sca.sca_launch(size, 1, 4, 1, 2)),
+            sca.sca_tune_entry(sca.SCA_F32, 1, 1, 8192, sca.sca_launch(size, 0, 4, 1, 2)),
+            sca.sca_tune_entry(sca.SCA_F32, 0, 1, 100, sca.sca_launch(size, 4, 2, 1, 1))]
+    sca.sca_tuning_set(good)
+    bad = [sca.sca_tune_entry(sca.SCA_F32, 1, 1, 8192, sca.sca_launch(size, 1, 3, 1, 2)),
+           sca.sca_tune_entry(sca.SCA_F32, 1, 1, 8192, sca.sca_launch(size, 1, 4, 1, 5)),
+           sca.sca_tune_entry(sca.SCA_F32, 0, 1, 100, sca.sca_launch(size, 4, 2, 1, 2)),
+           sca.sca_tune_entry(sca.SCA_F32, 2, 1, 100, sca.sca_launch(size, 1, 4, 2, 2))]
+    for row in bad:
+        with pytest.raises(sca.SCAError):
+            sca.sca_tuning_set([row])
+    sca.load_tuning()

@@ -44,9 +44,12 @@ def test_algorithmic_bytes_per_launch(bench):
 
 
 def test_kernel_names(bench):
-    assert bench.grad_kernel_name(FUSED, False, 20000) == "k_grad_br_fold<float,5,1>"
+    assert bench.grad_kernel_name(FUSED, False, 20000) == "k_grad_br_fold<float,5,1,0>"
     assert bench.grad_kernel_name(dict(FUSED, grad_cols=2), False, 10000) == \
-        "k_grad_br_fold<float,3,2>"
+        "k_grad_br_fold<float,3,2,0>"
+    # beyond 20480 rows: 4 row groups per thread in registers, 2 or 3 in LDS
+    assert bench.grad_kernel_name(FUSED, False, 24000) == "k_grad_br_fold<float,4,1,2>"
+    assert bench.grad_kernel_name(FUSED, False, 28672) == "k_grad_br_fold<float,4,1,3>"
     assert bench.grad_kernel_name(TWO_PASS, False, 20000) == "k_grad_br_wg<float,4,4,true>"
 
 
@@ -80,7 +83,7 @@ def test_counter_summary_scaling_and_fingerprint(bench, tmp_path, monkeypatch):
     the kernel's per-launch bytes are its mean KiB x 1024 x scale; the summary is used only
     while the kernel source and launch shape match its fingerprint."""
     gib_kib = (1 << 30) / 1024.0
-    kname = "void sca::k_grad_br_fold<float, 5, 1>(float const*, long long, int)"
+    kname = "void sca::k_grad_br_fold<float, 5, 1, 0>(float const*, long long, int)"
     fetch = _counter_dir(str(tmp_path), "fetch", "FETCH_SIZE",
                          [("k_stream_copy(...)", 2 * gib_kib)] * 3 +
                          [(kname, 2.0e6), (kname, 2.2e6), ("other_kernel", 5.0)])

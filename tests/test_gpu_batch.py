@@ -114,8 +114,9 @@ def test_batch_solve_reaches_tolerance_per_instance():
 
 
 def test_batch_graph_replays_match_eager_rounds():
-    """The solve replays a captured graph (rounds + fresh residual + check); with no
-    tolerance it must reproduce the eager rounds of sca_batch_step on every replay."""
+    """The solve replays a captured graph (rounds + check from the running residual); with no
+    tolerance (no instance is ever a candidate, so the running residual is never restarted)
+    it must reproduce the eager rounds of sca_batch_step on every replay."""
     ws = inputs.batch_lasso(4, m_range=(90, 300), nnz_frac=0.05, block=16, p=0.5,
                             dtype=torch.float64, seed=9)
     wd = [w.to("cuda") for w in ws]
@@ -129,6 +130,5 @@ def test_batch_graph_replays_match_eager_rounds():
         sca.sca_batch_residual(B.handle, xe, re)
         for k0 in range(0, rounds, 10):
             sca.sca_batch_step(B.handle, o, k0, 10, xe, re)
-            sca.sca_batch_residual(B.handle, xe, re)  # the solve refreshes r at every check
         torch.cuda.synchronize()
         assert torch.equal(xs, xe), rounds

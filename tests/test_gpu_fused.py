@@ -81,10 +81,12 @@ def _q(m, dtype):
 
 
 # (m, n, block, p, cols): Q = 1, 2, 3 for FP64 (2 rows per 16 bytes), ragged tails,
-# S < 256 workgroups (64 x 300), every block drawn, the largest FP64 m (6144)
+# S < 256 workgroups (64 x 300), every block drawn, the largest all-register FP64 m (6144);
+# then 3 row groups in registers and 1, 2, 3 in LDS (6145, 9999 ragged, 12288 the largest)
 FP64_CASES = [(517, 2050, 7, 1.0, 4), (2049, 3001, 64, 0.4, 2), (4097, 2500, 32, 0.3, 2),
               (5999, 2000, 32, 0.3, 1), (6144, 1500, 16, 0.5, 1), (64, 300, 1, 0.2, 4),
-              (1500, 4000, 64, 0.25, 1)]
+              (1500, 4000, 64, 0.25, 1), (6145, 1500, 16, 0.5, 1), (9999, 1200, 32, 0.4, 1),
+              (12288, 1000, 16, 0.5, 1)]
 
 
 @pytest.mark.parametrize("m,n,block,p,cols", FP64_CASES)
@@ -94,7 +96,7 @@ def test_fused_fp64_matches_oracle(m, n, block, p, cols):
     prob = _oracle(w)
     run = Run(w, cols=cols)
     assert run.launch["grad_kind"] == FUSED
-    assert _q(m, torch.float64) <= 3
+    assert _q(m, torch.float64) <= 6
     for i, (xo, ro) in enumerate(_trajectory(w, prob, 30, 5)):
         xg, rg = run.step(5)
         assert _rel(xg, xo) <= 1e-10, (i, _rel(xg, xo))
@@ -172,9 +174,11 @@ def test_fused_diminishing_stepsize_fp64():
 
 
 # FP32 (4 rows per 16 bytes): Q = 1 (C = 8), 2 (C = 4), 3 (C = 2), 4, and the largest
-# m (5 groups per thread, 20480 rows) with a ragged tail (16389 = 4 * 4097 + 1)
+# all-register m (5 groups per thread, 20480 rows) with a ragged tail (16389 = 4 * 4097 + 1);
+# then 4 groups in registers and 2 or 3 in LDS (20481, 24001 ragged, 28672 the largest)
 @pytest.mark.parametrize("m,n,cols", [(3000, 4000, 8), (5001, 3000, 4), (10000, 2500, 2),
-                                      (13000, 1500, 1), (16389, 1500, 1), (20480, 1200, 1)])
+                                      (13000, 1500, 1), (16389, 1500, 1), (20480, 1200, 1),
+                                      (20481, 1200, 1), (24001, 1000, 1), (28672, 1000, 1)])
 def test_fused_fp32_objective(m, n, cols):
     w = inputs.lasso_dense_fp32(m=m, n=n, seed=5)
     prob = _oracle(w)
@@ -222,7 +226,7 @@ def test_fused_determinism_resume_and_graph_solve():
 
 
 def test_fused_rejected_where_columns_do_not_fit():
-    cases = [(torch.float64, 6145), (torch.float32, 20481)]
+    cases = [(torch.float64, 12289), (torch.float32, 28673)]
     for dtype, m in cases:
         w = inputs.dense_problem(m, 64, nnz_frac=0.05, block=8, p=0.5, dtype=dtype,
                                  seed=9).to("cuda")
@@ -251,3 +255,22 @@ def test_fused_rejected_where_columns_do_not_fit():
     sca.sca_problem_set_launch(P.handle, FUSED, 8, 1, 1)
     assert sca.sca_problem_get_launch(P.handle)["grad_cols"] == 4
     P.close()
+
+
+@pytest.mark.parametrize("dtype,m", [(torch.float64, 9999), (torch.float32, 24001)])
+def test_fused_lds_row_groups_ignore_nan_padding_rows(dtype, m):
+    """Columns that spill into the LDS row groups: A's rows m..lda-1 (in the last, LDS
+    held, row group) set to NaN never reach x, r or the objective."""
+    w = inputs.dense_problem(m, 800, nnz_frac=0.02, lam_frac=0.02, block=16, p=0.5,
+                             dtype=dtype, seed=m % 97)
+    assert w.lda > w.m
+    prob = _oracle(w)
+    w.At[:, w.m:] = float("nan")
+    run = Run(w, cols=1)
+    assert run.launch["grad_kind"] == FUSED
+    xo, ro = _trajectory(w, prob, 10, 10)[-1]
+    xg, rg = run.step(10)
+    assert np.all(np.isfinite(xg)) and np.all(np.isfinite(rg))
+    tol = 1e-10 if dtype == torch.float64 else x_tol(m)
+    print(f"[parity] fused LDS rows {dtype} m={m}: x err {_rel(xg, xo):.2e}", flush=True)
+    assert _rel(xg, xo) <= tol and _rel(rg, ro) <= tol
