@@ -465,7 +465,7 @@ PMC_SUMMARY = {
 # sources whose kernels the counter runs measured (their digest is the summary's fingerprint)
 PMC_SOURCES = {"lasso": ("sca_kernels.h", "sca_device.h"),
                "sparse": ("sca_kernels.h", "sca_device.h", "sca_csc.hip")}
-SPARSE_STEP_KERNELS = ("k_dot_split<float,8>", "k_br_split<float,8>")
+SPARSE_STEP_KERNELS = ("k_dot_split<float,8,true>", "k_br_split<float,8>")
 CALIB_BYTES = 1 << 30
 
 
@@ -760,10 +760,11 @@ def round_alg_bytes(L, drawn, m, esize, groups):
 
 def grad_kernel_name(L, sparse, m=0):
     if sparse:
-        # panel split (r in at most 16 panels of 140 KiB): partial dot products, then the sum
-        # of the partials with the best response (one timed step, two kernels)
+        # panel split (r in at most 16 panels of 140 KiB): partial dot products (with the
+        # block draw inside: at most 32768 blocks, as in the sparse workloads here), then the
+        # sum of the partials with the best response (one timed step, two kernels)
         if (m + 35839) // 35840 <= 16:
-            return "k_dot_split<float,8> + k_br_split<float,8>"
+            return "k_dot_split<float,8,true> + k_br_split<float,8>"
         return "k_grad_br_cscp<float,8>"
     if L["grad_kind"] == 4:
         q = fused_q(m, 4)

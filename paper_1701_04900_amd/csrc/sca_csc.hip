@@ -406,6 +406,7 @@ k_grad_br_cscp(const long long* __restrict__ colptr, const int* __restrict__ row
 constexpr int kSplitPanelBytes = 143360;  // 140 KiB of r per workgroup
 constexpr int kSplitMaxPanels = 16;       // one partial per lane of a 16-lane group
 constexpr int kSplitStage = 12;           // r loads per thread in flight while staging
+constexpr int kSplitList = 2048;          // drawn columns listed in LDS at a time (in-kernel draw)
 
 // pofs of every column: a binary search per inner panel boundary.
 __global__ void __launch_bounds__(256)
@@ -440,46 +441,138 @@ k_panel_offsets(const long long* __restrict__ colptr, const int* __restrict__ ro
 // run reads entry 0, whose value is not used), so no load waits for another's result
 // except through a real dependence.  Lane sub adds the entries sub, sub + 16, ... in order;
 // part[P * ldpart + t] = the 16 lane sums added by sum16.
-template <typename T, int CPG>
+// DRAW: the block draw (S.1) runs here instead of in k_select: every workgroup draws every
+// block of round st->k (at most 32 per thread: the drawn flags and the first list position
+// of each thread's blocks are kept in LDS), scans the drawn columns in block order and lists
+// the columns of its chunk in LDS, kSplitList at a time; the workgroups of panel 0 also
+// write their chunk to sel_out for the kernels that follow, and workgroup 0 writes the
+// drawn count.  The round state is advanced after the fold (k_bin_scan).  Without DRAW the
+// list is sel_cols, walked in the same pieces.
+template <typename T, int CPG, bool DRAW>
 __global__ void __launch_bounds__(1024)
 k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
             const T* __restrict__ v, const T* __restrict__ r, const int* __restrict__ sel_cols,
-            const RoundState* __restrict__ st, int m, int NP, int PE, int CPP,
-            T* __restrict__ part, long long ldpart) {
+            RoundState* __restrict__ st, int m, int NP, int PE, int CPP,
+            T* __restrict__ part, long long ldpart, FusedSel fs, int* __restrict__ sel_out) {
   constexpr int PR = kSplitPanelBytes / (int)sizeof(T);
   constexpr int G = 1024 / 16;  // groups of 16 lanes
   constexpr int H = 3;          // 16-entry windows loaded at once per coordinate
   __shared__ T s_r[PR];
-  const int P = (int)blockIdx.x % NP, c = (int)blockIdx.x / NP;
+  __shared__ int s_list[DRAW ? kSplitList : 1];
+  __shared__ uint32_t s_dmask[DRAW ? 1024 : 1];
+  __shared__ int s_doff[DRAW ? 1024 : 1];
+  __shared__ int s_scan[17];
+  // the NP panels of one chunk run on one XCD: the cache lines their column runs share
+  // (a column's entries cross panel boundaries inside a line) are fetched into one L2
+  const int g = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  const int P = g % NP, c = g / NP;
   const int lo = P * PE, hi = min(m, lo + PE), len = max(0, hi - lo);
-  const int S = st->S_cnt;
+  const int dper = (fs.nblocks + 1023) / 1024;  // <= 32 (host check)
+  const int db0 = min(fs.nblocks, (int)threadIdx.x * dper);
+  const int db1 = min(fs.nblocks, db0 + dper);
+  int S;
+  if (DRAW) {
+    // this thread's blocks [db0, db1): block pointers loaded four blocks at a time (all
+    // loads in flight before the draws that use them), drawn flags, drawn column count
+    const long long k = st->k;
+    int cnt = 0;
+    uint32_t dm = 0;
+    for (int i0 = db0; i0 < db1; i0 += 4) {
+      int bv[5];
+#pragma unroll
+      for (int u = 0; u < 5; ++u) bv[u] = fs.bp[min(i0 + u, fs.nblocks)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u;
+        if (i < db1 && block_drawn((uint32_t)i, (uint64_t)k, fs.inst, fs.seed, fs.T)) {
+          cnt += bv[u + 1] - bv[u];
+          dm |= 1u << (i - db0);
+        }
+      }
+    }
+    s_dmask[threadIdx.x] = dm;
+    s_doff[threadIdx.x] = block_exclusive_scan_1024(cnt, s_scan, &S);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->S_cnt = S;
+    __syncthreads();  // s_doff of the next thread is read below
+  } else {
+    S = st->S_cnt;
+  }
+  S = __builtin_amdgcn_readfirstlane(S);  // uniform: the chunk bounds stay in scalar registers
+  // the columns of list positions [p0, p1) into s_list (panel 0 also writes them to
+  // sel_out).  Only threads whose drawn columns [s_doff[t], s_doff[t + 1]) meet [p0, p1)
+  // have blocks to list; each wave lists its lanes' blocks together, one block at a time,
+  // 64 positions per store.
+  auto expand = [&](int p0, int p1) {
+    const int lane = threadIdx.x & 63;
+    uint32_t dm = s_dmask[threadIdx.x];
+    int o = s_doff[threadIdx.x];
+    const int oend = threadIdx.x + 1 < 1024 ? s_doff[threadIdx.x + 1] : S;
+    if (oend <= p0 || o >= p1) dm = 0;
+    for (;;) {
+      int cb = 0, oo = 0, a = 0, b = 0;
+      bool have = false;
+      while (dm != 0 && o < p1) {  // this thread's next drawn block that meets [p0, p1)
+        const int i = db0 + __builtin_ctz(dm);
+        dm &= dm - 1;
+        const int c0b = fs.bp[i], ln = fs.bp[i + 1] - c0b;
+        const int aa = max(o, p0), bb = min(o + ln, p1);
+        oo = o;
+        o += ln;
+        if (aa < bb) {
+          cb = c0b;
+          a = aa;
+          b = bb;
+          have = true;
+          break;
+        }
+      }
+      uint64_t bal = __ballot(have);
+      if (bal == 0) break;
+      while (bal) {
+        const int l = __builtin_ctzll(bal);
+        bal &= bal - 1;
+        const int cbl = __shfl(cb, l), ool = __shfl(oo, l);
+        const int al = __shfl(a, l), bl = __shfl(b, l);
+        for (int t = al + lane; t < bl; t += 64) {
+          const int col = cbl + (t - ool);
+          s_list[t - p0] = col;
+          if (P == 0) sel_out[t] = col;
+        }
+      }
+    }
+  };
   const int per = (S + CPP - 1) / CPP;
   const int c0 = min(S, c * per), c1 = min(S, c0 + per);
   const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int NP1 = NP + 1;
+  int p0 = c0, p1 = min(c1, c0 + kSplitList);
+  if (DRAW) {
+    expand(p0, p1);
+    __syncthreads();
+  }
   // drawn columns of the coordinates tb + grp + G * i, then their panel offsets [a, b)
-  // (an empty run past c1); the list is read two passes ahead, the offsets one
+  // (an empty run past p1); the list is read two passes ahead, the offsets one
   auto load_cols = [&](int tb, int (&jr)[CPG]) {
 #pragma unroll
     for (int i = 0; i < CPG; ++i) {
       const int t = tb + grp + G * i;
-      jr[i] = sel_cols[t < c1 ? t : 0];
+      jr[i] = DRAW ? s_list[t < p1 ? t - p0 : 0] : sel_cols[t < p1 ? t : 0];
     }
   };
   auto load_offs = [&](int tb, const int (&jr)[CPG], int (&a)[CPG], int (&b)[CPG]) {
 #pragma unroll
     for (int i = 0; i < CPG; ++i) {
       const int t = tb + grp + G * i;
-      const size_t o = (size_t)(t < c1 ? jr[i] : 0) * NP1 + P;
+      const size_t o = (size_t)(t < p1 ? jr[i] : 0) * NP1 + P;
       a[i] = pofs[o];
-      b[i] = pofs[o + (t < c1 ? 1 : 0)];
+      b[i] = pofs[o + (t < p1 ? 1 : 0)];
     }
   };
   int jn[CPG], ks[CPG], ke[CPG];
-  if (c0 < c1) {  // in flight while r's panel is staged
-    load_cols(c0, jn);
-    load_offs(c0, jn, ks, ke);
-    load_cols(c0 + G * CPG, jn);
+  if (p0 < p1) {  // in flight while r's panel is staged
+    load_cols(p0, jn);
+    load_offs(p0, jn, ks, ke);
+    load_cols(p0 + G * CPG, jn);
   }
   for (int base = 0; base < len; base += 1024 * kSplitStage) {
     T tmp[kSplitStage];
@@ -495,7 +588,8 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
     }
   }
   __syncthreads();
-  for (int tb = c0; tb < c1; tb += G * CPG) {
+  for (;;) {
+  for (int tb = p0; tb < p1; tb += G * CPG) {
     int rw[CPG][H];
     T vw[CPG][H];
 #pragma unroll
@@ -541,7 +635,7 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
       }
       acc = sum16(acc);
       const int t = tb + grp + G * i;
-      if (sub == 0 && t < c1) part[(size_t)P * ldpart + t] = acc;
+      if (sub == 0 && t < p1) part[(size_t)P * ldpart + t] = acc;
     }
 #pragma unroll
     for (int i = 0; i < CPG; ++i) {
@@ -549,27 +643,41 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
       ke[i] = ke2[i];
     }
   }
+  // the next piece of the chunk (only when it holds more than kSplitList columns)
+  if (p1 >= c1) break;
+  __syncthreads();  // every group is done with s_list
+  p0 = p1;
+  p1 = min(c1, p0 + kSplitList);
+  if (DRAW) {
+    expand(p0, p1);
+    __syncthreads();
+  }
+  load_cols(p0, jn);
+  load_offs(p0, jn, ks, ke);
+  load_cols(p0 + G * CPG, jn);
+  }
 }
 
 // S.2 (second half) + S.4 after k_dot_split: the NP partials of each drawn coordinate are
 // added by sum16 (lane sub holds panel sub's), then the best response and the step; the
 // moved columns' nonzeros are counted per row bin (64 entries of every moved column per
 // step).  Loads are unconditional as in k_dot_split.  Same work mapping and outputs as
-// k_grad_br_csc.
+// k_grad_br_csc.  gnext: the draw ran in k_dot_split and the round state is not advanced
+// yet, so the round's step is st->gamma_next.
 template <typename T, int CPG>
 __global__ void __launch_bounds__(kCscThreads)
 k_br_split(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
            const T* __restrict__ part, long long ldpart, int NP, T* __restrict__ x,
            const double* __restrict__ cn2, const int* __restrict__ sel_cols,
            const RoundState* __restrict__ st, T* __restrict__ dx_sel, BRParams bp, int bin_log,
-           int nb, int* __restrict__ cnt, int* __restrict__ moved_wg) {
+           int nb, int* __restrict__ cnt, int* __restrict__ moved_wg, int gnext) {
   extern __shared__ int hist[];
   __shared__ int s_moved[kCscThreads / 64];
   for (int i = threadIdx.x; i < nb; i += kCscThreads) hist[i] = 0;
   __syncthreads();
   constexpr int G = kCscThreads / 16;
   const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
-  const T gamma = (T)st->gamma_cur;
+  const T gamma = (T)(gnext ? st->gamma_next : st->gamma_cur);
   int c0, c1;
   wg_chunk(st->S_cnt, &c0, &c1);
   int moved = 0;
@@ -656,11 +764,12 @@ k_bin_hist(const long long* __restrict__ colptr, const int* __restrict__ rowidx,
 // cnt[w][bin] -> exclusive prefix over w inside each bin; tot[bin] = bin total.  One
 // workgroup per bin; thread i takes a run of consecutive w (all its loads in flight at
 // once), then a block scan orders the runs.  Block 0 also adds the moved columns of the
-// round to the running statistics.
+// round to the running statistics and, with advance (the draw ran inside the gradient
+// kernel), advances the round as k_select does: drawn count, round counter, step.
 template <int PER>
 __global__ void __launch_bounds__(256)
 k_bin_scan(int* __restrict__ cnt, int grid, int nb, int* __restrict__ tot,
-           const int* __restrict__ moved_wg, RoundState* __restrict__ st) {
+           const int* __restrict__ moved_wg, RoundState* __restrict__ st, int advance) {
   __shared__ int sh[5];
   __shared__ long long s_mv[4];
   const int bin = blockIdx.x;
@@ -686,7 +795,17 @@ k_bin_scan(int* __restrict__ cnt, int grid, int nb, int* __restrict__ tot,
     mv = wave_sum_i64(mv);
     if ((threadIdx.x & 63) == 0) s_mv[threadIdx.x >> 6] = mv;
     __syncthreads();
-    if (threadIdx.x == 0) st->moved_updates += s_mv[0] + s_mv[1] + s_mv[2] + s_mv[3];
+    if (threadIdx.x == 0) {
+      st->moved_updates += s_mv[0] + s_mv[1] + s_mv[2] + s_mv[3];
+      if (advance) {
+        const double g = st->gamma_next;
+        st->coord_updates += st->S_cnt;
+        st->k += 1;
+        st->work_ctr = 0;
+        st->gamma_cur = g;
+        st->gamma_next = g * (1.0 - st->gamma_mu * g);
+      }
+    }
   }
 }
 
@@ -958,14 +1077,14 @@ k_probe_csc(const long long* __restrict__ colptr, const int* __restrict__ rowidx
 template <typename T, typename TB, typename TO>
 void bin_fold(sca_problem* p, const int* list, const int* count_ptr, int count, const T* coef,
               const int* moved_wg, const TB* base, double base_scale, TO* out, double* out64,
-              hipStream_t s) {
+              hipStream_t s, int advance = 0) {
   const int nb = p->bin_nb, grid = p->bin_grid;
   if (grid <= 256 * 4)
     hipLaunchKernelGGL(k_bin_scan<4>, dim3(nb), dim3(256), 0, s, p->d_bin_cnt, grid, nb,
-                       p->d_bin_tot, moved_wg, p->d_state);
+                       p->d_bin_tot, moved_wg, p->d_state, advance);
   else
     hipLaunchKernelGGL(k_bin_scan<kBinGridMax / 256>, dim3(nb), dim3(256), 0, s, p->d_bin_cnt,
-                       grid, nb, p->d_bin_tot, moved_wg, p->d_state);
+                       grid, nb, p->d_bin_tot, moved_wg, p->d_state, advance);
   if (p->bin_unroll == 2)
     hipLaunchKernelGGL((k_bin_scatter<T, 2>), dim3(grid), dim3(kCscThreads), sizeof(int) * nb, s,
                        (const long long*)p->csc_colptr, (const int*)p->csc_rowidx,
@@ -996,21 +1115,29 @@ void grad_launch(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream
                      p->bin_log, p->bin_nb, p->d_bin_cnt, p->d_bin_moved);
 }
 
+// fs.on (panel split only): the block draw runs inside k_dot_split.
 template <typename T>
-void grad_any(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream_t s) {
+void grad_any(sca_problem* p, T* x, const T* r, const BRParams& bp, const FusedSel& fs,
+              hipStream_t s) {
   if (p->sp_np > 0) {
     constexpr int CPG = sizeof(T) == 4 ? 8 : 4;
     const int NP = p->sp_np, CPP = std::max(1, p->ncu / NP);
     const long long ldpart = std::max<long long>(1, p->n);
-    hipLaunchKernelGGL((k_dot_split<T, CPG>), dim3(NP * CPP), dim3(1024), 0, s,
-                       (const int*)p->d_pofs, (const int*)p->csc_rowidx, (const T*)p->csc_vals,
-                       r, p->d_sel_cols, (const RoundState*)p->d_state, (int)p->m, NP, p->sp_pe,
-                       CPP, (T*)p->d_sp_part, ldpart);
+    if (fs.on)
+      hipLaunchKernelGGL((k_dot_split<T, CPG, true>), dim3(NP * CPP), dim3(1024), 0, s,
+                         (const int*)p->d_pofs, (const int*)p->csc_rowidx, (const T*)p->csc_vals,
+                         r, p->d_sel_cols, p->d_state, (int)p->m, NP, p->sp_pe, CPP,
+                         (T*)p->d_sp_part, ldpart, fs, p->d_sel_cols);
+    else
+      hipLaunchKernelGGL((k_dot_split<T, CPG, false>), dim3(NP * CPP), dim3(1024), 0, s,
+                         (const int*)p->d_pofs, (const int*)p->csc_rowidx, (const T*)p->csc_vals,
+                         r, p->d_sel_cols, p->d_state, (int)p->m, NP, p->sp_pe, CPP,
+                         (T*)p->d_sp_part, ldpart, fs, p->d_sel_cols);
     hipLaunchKernelGGL((k_br_split<T, CPG>), dim3(p->bin_grid), dim3(kCscThreads),
                        sizeof(int) * p->bin_nb, s, (const long long*)p->csc_colptr,
                        (const int*)p->csc_rowidx, (const T*)p->d_sp_part, ldpart, NP, x,
                        p->d_cn2, p->d_sel_cols, (const RoundState*)p->d_state, (T*)p->d_dx_sel,
-                       bp, p->bin_log, p->bin_nb, p->d_bin_cnt, p->d_bin_moved);
+                       bp, p->bin_log, p->bin_nb, p->d_bin_cnt, p->d_bin_moved, fs.on);
   } else if (p->bin_panel) {
     hipLaunchKernelGGL((k_grad_br_cscp<T, sizeof(T) == 4 ? 8 : 4>), dim3(p->bin_grid),
                        dim3(kPanelThreads), 0, s,
@@ -1027,19 +1154,25 @@ void grad_any(sca_problem* p, T* x, const T* r, const BRParams& bp, hipStream_t 
   }
 }
 
+// The panel-split gradient draws the round's blocks itself when every thread of its
+// 1024-thread workgroups owns at most 32 of them.
 template <typename T>
 void round_csc(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s, uint64_t Tthr,
                const BRParams& bp) {
-  prof_begin(p, s, SCA_K_SELECT);
-  launch_select(p, o, Tthr, s);
-  prof_end(p, s, 0.0);
+  FusedSel fs{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
+  fs.on = p->sp_np > 0 && p->nblocks <= kFusedSelBlocks;
+  if (!fs.on) {
+    prof_begin(p, s, SCA_K_SELECT);
+    launch_select(p, o, Tthr, s);
+    prof_end(p, s, 0.0);
+  }
   prof_begin(p, s, SCA_K_GRAD);
-  grad_any<T>(p, x, r, bp, s);
+  grad_any<T>(p, x, r, bp, fs, s);
   prof_end(p, s, 0.0);
   prof_begin(p, s, SCA_K_FOLD);
   int* S_ptr = (int*)((char*)p->d_state + offsetof(RoundState, S_cnt));
   bin_fold<T, T, T>(p, p->d_sel_cols, S_ptr, 0, (const T*)p->d_dx_sel, p->d_bin_moved, r, 1.0,
-                    r, (double*)nullptr, s);
+                    r, (double*)nullptr, s, fs.on);
   prof_end(p, s, 0.0);
 }
 

@@ -71,6 +71,16 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs round robin (workgroup w to XCD w % 8), and
+// each XCD has an L2 of its own.  xcd_order(w, W) is a position in [0, W) such that the
+// workgroups of one XCD take one contiguous range of positions: workgroups whose positions
+// are neighbours (and that read neighbouring data) then share an L2.  A bijection of [0, W).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_order(int w, int W) {
+  const int x = w % kXcds, q = w / kXcds;
+  return x * (W / kXcds) + min(x, W % kXcds) + q;
+}
+
 // Exclusive scan over a 1024-thread block (16 waves); returns the prefix, *total = sum.
 // 'sh' needs 17 ints of shared memory.  Contains __syncthreads.
 __device__ __forceinline__ int block_exclusive_scan_1024(int v, int* sh, int* total) {

@@ -60,7 +60,7 @@ def test_sparse_kernel_names_follow_the_library_panel_limits(bench):
     panel_bytes = int(re.search(r"constexpr int kSplitPanelBytes = (\d+);", src).group(1))
     max_panels = int(re.search(r"constexpr int kSplitMaxPanels = (\d+);", src).group(1))
     rows = panel_bytes // 4
-    split = "k_dot_split<float,8> + k_br_split<float,8>"
+    split = "k_dot_split<float,8,true> + k_br_split<float,8>"
     assert bench.grad_kernel_name(TWO_PASS, True, 100000) == split
     assert bench.grad_kernel_name(TWO_PASS, True, rows * max_panels) == split
     assert bench.grad_kernel_name(TWO_PASS, True, rows * max_panels + 1) == \
@@ -119,7 +119,7 @@ def test_sparse_counter_summary_adds_both_step_kernels(bench, tmp_path, monkeypa
     """The sparse gradient step is two kernels: their per-launch bytes are added; the
     algorithmic bytes are (4 B value + 4 B row) per nonzero of the drawn columns."""
     gib_kib = (1 << 30) / 1024.0
-    dot = "void (anonymous namespace)::k_dot_split<float, 8>(int const*, int const*)"
+    dot = "void (anonymous namespace)::k_dot_split<float, 8, true>(int const*, int const*)"
     br = "void (anonymous namespace)::k_br_split<float, 8>(long long const*, int const*)"
     fetch = _counter_dir(str(tmp_path), "fetch", "FETCH_SIZE",
                          [("k_stream_copy(...)", 2 * gib_kib)] * 3 +
