@@ -143,6 +143,7 @@ def cpu_baseline(w, opts_kw, rounds):
     x, r, upd = O.run_rounds(prob, cfg, x, r, 0, rounds)
     dt = time.perf_counter() - t0
     return dict(value=upd / dt, unit="coord-updates/s", cores=int(threads), kind="oracle",
+                seconds_per_round=dt / rounds,
                 sample=f"{rounds} rounds from x=0 of the same {what} "
                        f"({upd} coordinate updates in {dt:.1f} s, FP64 numpy)")
 
@@ -1032,6 +1033,13 @@ def run_single(kind, args, steps, warmup, seeds=1, profile=True, cpu_rounds=None
         "profiled_pass": prof_pass,
         "cpu_baseline": cpu,
     }
+    if cpu:
+        # the oracle draws the same blocks and follows the same trajectory (in FP64), so it
+        # needs about as many rounds: its time for them, from its measured time per round
+        cpu["rounds_extrapolated_to"] = rounds / steps
+        cpu["time_extrapolated_s"] = cpu["seconds_per_round"] * rounds / steps
+        cpu["extrapolation"] = ("seconds per round of the sample x the GPU's rounds per step "
+                                "(not run: the oracle takes that long)")
     if milestones:
         out["merit_milestones"] = milestones
     if per_seed:
