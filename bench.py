@@ -417,7 +417,8 @@ def bench_multi(args):
 def bench_delay(args):
     """Bounded-delay rounds on the 20000 x 100000 FP32 LASSO: rounds and time to relative
     error 1e-6 for several (groups q, staleness s); every update misses at most
-    (s + 1) ceil(|S|/q) - 1 others (|S| ~ 25000 drawn coordinates per round)."""
+    (s + 1) ceil(|S|/q) - 1 others (|S| ~ 25000 drawn coordinates per round).  Then lock-free
+    rounds on W racing workgroups (each update misses at most W - 1 others)."""
     w = inputs.lasso_dense_fp32(m=args.m, n=args.n, seed=0, device="cuda")
     okw = dict(gamma=w.gamma, tau=w.tau, select_p=w.p, seed=w.seed)
     F_star, _ = reference_optimum(w, okw)
@@ -447,6 +448,22 @@ def bench_delay(args):
         if q == 1:
             value = upd / el
             base_ms = el * 1e3
+    # lock-free rounds: W workgroups race on the round's drawn coordinates (nondeterministic);
+    # each update misses at most W - 1 others in flight.  One solve each (atomic folds: slow)
+    for W in (256, 1024, 4096):
+        o = sca.make_opts(**okw, max_rounds=5000, check_every=10, tol_rel_obj=args.tol,
+                          F_star=F_star, async_workgroups=W)
+        x = torch.zeros(w.n, dtype=w.dtype, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sca.sca_solve(P.handle, o, x, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rows.append(dict(lock_free_workgroups=W, delay_bound=W - 1, rounds=st["rounds"],
+                         time_to_tol_s=el, coord_updates_per_s=st["coord_updates"] / el,
+                         rel_err=st["rel_err"], status=st["status"]))
+        log(f"lock-free W={W}: delay bound {W - 1}, {st['rounds']} rounds, {el * 1e3:.1f} ms, "
+            f"rel err {st['rel_err']:.2e}")
     out = {
         "metric": METRIC, "value": value, "unit": "coord-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": base_ms, "higher_is_better": True,

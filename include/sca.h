@@ -82,6 +82,7 @@ typedef struct {
   double tol_merit;      /* sca_solve: stop at ||xh(x) - x||_inf <= tol (0 = off)          */
   int64_t delay_chunks;  /* > 1: bounded-delay rounds (dense problems only; see below)     */
   int64_t delay_stale;   /* staleness of the bounded-delay rounds, in groups (>= 0)        */
+  int64_t async_workgroups; /* > 0: lock-free rounds on this many workgroups (see below)   */
 } sca_opts;
 
 /* Bounded-delay rounds (delayed iterates of Algorithm 1, delays bounded as in Assumption
@@ -91,7 +92,18 @@ typedef struct {
  * then misses at most (delay_stale + 1) * ceil(|S|/q) - 1 others.  q <= 1, or
  * delay_stale >= q - 1, is the ordinary round (all drawn coordinates read the same
  * iterate); delay_stale = 0 is a Gauss-Seidel sweep over the groups.  Deterministic.  The
- * sparse, batched and multi-right-hand-side paths reject delay_chunks > 1 (SCA_EINVAL). */
+ * sparse, batched and multi-right-hand-side paths reject delay_chunks > 1 (SCA_EINVAL).
+ *
+ * Lock-free rounds (Algorithm 1 with the delays of Assumption D1 left to the hardware, as in
+ * the paper's shared-memory implementation, Section 4): with async_workgroups = W in
+ * [1, 65536] the drawn coordinates of a round are taken one at a time from a shared counter
+ * by W workgroups; each reads the residual r as it stands in device memory (it may miss the
+ * folds of the at most W - 1 coordinates in flight on other workgroups), updates its own
+ * x_j and folds its move into r with atomic adds.  The result depends on the timing for
+ * W > 1 (not reproducible run to run); W = 1 is a sequential sweep over the drawn
+ * coordinates in ascending order.  Dense problems only, and not with delay_chunks > 1
+ * (SCA_EINVAL); for a study of the delay's effect, not for speed (one atomic add per row of
+ * every moved column). */
 
 typedef struct {
   size_t struct_size;    /* = sizeof(sca_stats)                                          */

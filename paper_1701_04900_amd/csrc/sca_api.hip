@@ -58,6 +58,10 @@ sca_status sca::validate_opts(const sca_opts* o) {
     return set_error(SCA_EINVAL, "select_p must lie in (0, 1]");
   if (o->delay_chunks < 0 || o->delay_chunks > (1 << 20) || o->delay_stale < 0)
     return set_error(SCA_EINVAL, "delay_chunks must lie in [0, 2^20] and delay_stale be >= 0");
+  if (o->async_workgroups < 0 || o->async_workgroups > kAsyncMaxWorkgroups)
+    return set_error(SCA_EINVAL, "async_workgroups must lie in [0, %d]", kAsyncMaxWorkgroups);
+  if (o->async_workgroups > 0 && o->delay_chunks > 1)
+    return set_error(SCA_EINVAL, "lock-free rounds and bounded-delay rounds exclude each other");
   return SCA_OK;
 }
 
@@ -776,6 +780,78 @@ static void launch_round_delayed(sca_problem* p, const sca_opts* o, T* x, T* r, 
   hipLaunchKernelGGL(k_mb_finish, dim3(1), dim3(1), 0, s, p->d_state, p->d_mbstate);
 }
 
+// ------------------------------------------------------------------ lock-free rounds
+// Asynchronous rounds with real races (Algorithm 1 with the delays of Assumption D1 left to
+// the hardware): after the draw, W workgroups take the round's drawn coordinates one at a
+// time from the round's work counter.  For coordinate j a workgroup reads a_j and the
+// residual r as it stands in memory (relaxed agent-scope loads, so every read sees the
+// folds that have reached the L2 by then, and misses those of the at most W - 1 coordinates
+// in flight on other workgroups), forms the partial gradient, the best response and the
+// step (S.2-S.4; x_j is its own: D4) and folds d * a_j into r with one atomic add per row
+// (S.5).  Nondeterministic for W > 1 (the order of the atomic adds and of the reads); W = 1
+// is a sequential sweep over the drawn coordinates in ascending order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_async_round(const T* __restrict__ A, long long lda, int m, T* r, T* __restrict__ x,
+              const double* __restrict__ cn2, const int* __restrict__ sel_cols,
+              RoundState* __restrict__ st, BRParams bp) {
+  __shared__ int s_t;
+  __shared__ T s_red[4];
+  __shared__ T s_d;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int S = st->S_cnt;
+  const T gamma = (T)st->gamma_cur;
+  long long moved = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(&st->work_ctr, 1);
+    __syncthreads();
+    const int t = s_t;
+    if (t >= S) break;
+    const int j = sel_cols[t];
+    const T* a = A + (size_t)j * lda;
+    T acc = (T)0;
+    for (int i = threadIdx.x; i < m; i += 256)
+      acc += a[i] * __hip_atomic_load(&r[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    acc = wave_sum(acc);
+    if (lane == 0) s_red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const T dot = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+      const T xj = x[j];
+      T g = dot - (T)bp.c2 * xj;
+      if (bp.reg) g -= (T)bp.lam * dh_minus<T>(xj, bp);
+      const T q = (T)(cn2[j] + bp.tau);
+      const T xh = soft_clip<T>(xj - g / q, (T)bp.lam_eta / q, (T)bp.beta);
+      const T d = gamma * (xh - xj);
+      x[j] = xj + d;
+      s_d = d;
+      moved += d != (T)0;
+    }
+    __syncthreads();
+    const T d = s_d;
+    if (d != (T)0)
+      for (int i = threadIdx.x; i < m; i += 256) unsafeAtomicAdd(&r[i], a[i] * d);
+    __threadfence();  // this coordinate's folds are in memory before the next one's reads
+    __syncthreads();  // s_t, s_red and s_d are written again by the next coordinate
+  }
+  if (threadIdx.x == 0 && moved)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&st->moved_updates),
+              (unsigned long long)moved);
+}
+
+template <typename T>
+static void launch_round_async(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
+                               uint64_t Tthr, const BRParams& bp) {
+  prof_begin(p, s, SCA_K_SELECT);
+  launch_select(p, o, Tthr, s);  // also resets the work counter
+  prof_end(p, s, 0.0);
+  prof_begin(p, s, SCA_K_GRAD);
+  hipLaunchKernelGGL(k_async_round<T>, dim3((unsigned)o->async_workgroups), dim3(256), 0, s,
+                     (const T*)p->A, (long long)p->lda, (int)p->m, r, x,
+                     (const double*)p->d_cn2, (const int*)p->d_sel_cols, p->d_state, bp);
+  prof_end(p, s, 0.0);
+}
+
 // Fresh residual with FP64 accumulation: r64 = A x - b (and r_out in the dtype if given).
 template <typename T>
 static void launch_residual_dense(sca_problem* p, const T* x, T* r_out, hipStream_t s) {
@@ -836,6 +912,8 @@ static void run_rounds_t(sca_problem* p, const sca_opts* o, int64_t nrounds, T* 
   for (int64_t i = 0; i < nrounds; ++i) {
     if (p->sparse)
       launch_round_csc(p, o, (void*)x, (void*)r, s, Tthr, bp);
+    else if (o->async_workgroups > 0)
+      launch_round_async<T>(p, o, x, r, s, Tthr, bp);
     else if (delayed)
       launch_round_delayed<T>(p, o, x, r, s, Tthr, bp);
     else
@@ -892,6 +970,8 @@ void sca::init_round_state(sca_problem* p, const sca_opts* o, int64_t round_begi
 // Bounded-delay rounds: dense problems only; their residual versions are allocated here
 // (outside any graph capture).
 static sca_status prepare_delay(sca_problem* p, const sca_opts* o) {
+  if (o->async_workgroups > 0 && p->sparse)
+    return set_error(SCA_EINVAL, "lock-free rounds need a dense problem");
   if (o->delay_chunks <= 1) return SCA_OK;
   if (p->sparse) return set_error(SCA_EINVAL, "bounded-delay rounds need a dense problem");
   return ensure_ring(p, ring_slots_for(o));

@@ -1406,8 +1406,9 @@ extern "C" sca_status sca_batch_step(sca_batch* B, const sca_opts* o, int64_t ro
   if (!B) return set_error(SCA_EINVAL, "batch is NULL");
   sca_status st = validate_opts(o);
   if (st != SCA_OK) return st;
-  if (o->delay_chunks > 1)
-    return set_error(SCA_EINVAL, "bounded-delay rounds need the single-problem dense path");
+  if (o->delay_chunks > 1 || o->async_workgroups > 0)
+    return set_error(SCA_EINVAL,
+                     "bounded-delay and lock-free rounds need the single-problem dense path");
   if (round_begin < 0 || nrounds < 0 || !x || !r)
     return set_error(SCA_EINVAL, "bad round range or NULL x / r");
   if (((uintptr_t)r) % 16 || ((uintptr_t)x) % B->esize)
@@ -1479,8 +1480,9 @@ extern "C" sca_status sca_batch_solve(sca_batch* B, const sca_opts* o, void* x,
   if (!B || !x) return set_error(SCA_EINVAL, "NULL argument");
   sca_status st = validate_opts(o);
   if (st != SCA_OK) return st;
-  if (o->delay_chunks > 1)
-    return set_error(SCA_EINVAL, "bounded-delay rounds need the single-problem dense path");
+  if (o->delay_chunks > 1 || o->async_workgroups > 0)
+    return set_error(SCA_EINVAL,
+                     "bounded-delay and lock-free rounds need the single-problem dense path");
   if (o->max_rounds < 0 || o->check_every < 1)
     return set_error(SCA_EINVAL, "max_rounds >= 0 and check_every >= 1");
   if (stats)

@@ -98,6 +98,9 @@ struct sca_problem {
 };
 
 namespace sca {
+
+// lock-free rounds: most workgroups sca_opts.async_workgroups may ask for
+constexpr int kAsyncMaxWorkgroups = 65536;
 sca_status set_error(sca_status st, const char* fmt, ...);
 sca_status validate_opts(const sca_opts* o);
 sca_status dev_alloc(void** p, size_t bytes);

@@ -803,6 +803,8 @@ sca_status mcheck_opts(const sca_multi* M, const sca_opts* o) {
   if (st != SCA_OK) return st;
   if (!(M->cn2_min + o->tau > 0.0))
     return set_error(SCA_EINVAL, "min ||a_j||^2 + tau must be > 0");
+  if (o->async_workgroups > 0)
+    return set_error(SCA_EINVAL, "lock-free rounds need the single-problem dense path");
   return SCA_OK;
 }
 

@@ -39,7 +39,8 @@ class sca_opts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("check_every", ctypes.c_int64),
                 ("refresh_every", ctypes.c_int64), ("tol_rel_obj", ctypes.c_double),
                 ("F_star", ctypes.c_double), ("tol_merit", ctypes.c_double),
-                ("delay_chunks", ctypes.c_int64), ("delay_stale", ctypes.c_int64)]
+                ("delay_chunks", ctypes.c_int64), ("delay_stale", ctypes.c_int64),
+                ("async_workgroups", ctypes.c_int64)]
 
 
 class sca_stats(ctypes.Structure):
@@ -224,10 +225,10 @@ def _dtype_code(dt):
 
 def make_opts(gamma=0.9, tau=0.0, select_p=1.0, seed=0, instance=0, gamma_mu=0.0, flags=0,
               max_rounds=0, check_every=10, refresh_every=0, tol_rel_obj=0.0, F_star=0.0,
-              tol_merit=0.0, delay_chunks=0, delay_stale=0) -> sca_opts:
+              tol_merit=0.0, delay_chunks=0, delay_stale=0, async_workgroups=0) -> sca_opts:
     return sca_opts(ctypes.sizeof(sca_opts), gamma, gamma_mu, tau, select_p, seed, instance,
                     flags, max_rounds, check_every, refresh_every, tol_rel_obj, F_star, tol_merit,
-                    delay_chunks, delay_stale)
+                    delay_chunks, delay_stale, async_workgroups)
 
 
 TUNING_PATH = os.path.join(_HERE, "tuning", "gfx950.json")
