@@ -361,7 +361,7 @@ def bench_multi(args):
         achieved = gflop / (g["ms"] * 1e-3) / 1e12
         roof = dict(bound="mfma", achieved=round(achieved, 2), peak=MFMA_FP32_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
-                    traffic=None, kernel="k_mgrad<float,float,4>",
+                    traffic=None, kernel="k_mgrad_dma<4,16>" if K > 48 else "k_mgrad<float,float,%d>" % ((K + 15) // 16),
                     avg_launch_ms=round(g["ms"] / g["launches"], 4),
                     alg_flop_per_launch=round(gflop / g["launches"]))
         prof_pass = dict(ms_per_step=pel / args.steps * 1e3,

@@ -214,3 +214,34 @@ def test_multi_fp32_ragged_rows_with_nan_padding():
         print(f"[parity] multi fp32 m={w.m} problem {k}: x err {_rel(X[k].double().cpu().numpy(), x):.2e}", flush=True)
         assert _rel(X[k].double().cpu().numpy(), x) <= x_tol(w.m), k
     M.close()
+
+
+@pytest.mark.parametrize("m,n,K,nan_pad", [(1001, 3000, 64, True), (100, 900, 60, False),
+                                           (4100, 6000, 64, False)])
+def test_multi_fp32_64_problem_gradient_edges(m, n, K, nan_pad):
+    """The FP32 path at 33-64 problems (the direct-to-LDS gradient kernel): ragged m with the
+    last row quad straddling m and A's padding rows NaN, splits left empty (m = 100 over 16
+    row splits), fewer problems than the 64 padded ones (K = 60: the padding problems' R rows
+    must not enter), and partial coordinate tiles; per-problem iterates and objectives against
+    the oracle."""
+    w = inputs.multi_rhs_problem(m, n, K, rhs="perturbed" if K < 64 else "sweep", block=16,
+                                 p=0.37, dtype=torch.float32, seed=31 + m)
+    probs = {k: _oracle(w, k) for k in (0, K // 2, K - 1)}
+    if nan_pad:
+        assert w.lda > w.m
+        w.At[:, w.m:] = float("nan")
+    M, X, R = _setup(w)
+    o = _opts(w)
+    sca.sca_multi_step(M.handle, o, 0, 20, X, R)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(X).all()) and bool(torch.isfinite(R[:, : w.m]).all())
+    rep = sca.sca_multi_objective(M.handle, o, X, w.K)
+    for k, prob in probs.items():
+        x, r, _ = O.run_rounds(prob, _cfg(w), np.zeros(w.n), O.residual(prob, np.zeros(w.n)), 0,
+                               20)
+        Fo = O.objective(prob, x, r)
+        ex = _rel(X[k].double().cpu().numpy(), x)
+        print(f"[parity] multi fp32 m={w.m} K={K} problem {k}: x err {ex:.2e}", flush=True)
+        assert abs(rep["F"][k] - Fo) <= 1e-4 * abs(Fo), k
+        assert ex <= x_tol(w.m), k
+    M.close()
