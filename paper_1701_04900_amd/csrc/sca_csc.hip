@@ -604,13 +604,16 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
     int ks2[CPG], ke2[CPG];
     load_offs(tb + G * CPG, jn, ks2, ke2);
     load_cols(tb + 2 * G * CPG, jn);
-    // r at the window rows (row lo for lanes past the run: read, not used)
+    // r at the window rows.  Lanes past the run read entry 0's row clamped into the panel
+    // (read, not used): the index never depends on the run test, so the compiler keeps
+    // every row load unconditional (a load it sinks under the test is followed by a wait
+    // for every load in flight, the next pass's prefetches included).
+    const unsigned rmax = (unsigned)max(len - 1, 0);
     T rv[CPG][H];
 #pragma unroll
     for (int i = 0; i < CPG; ++i)
 #pragma unroll
-      for (int h = 0; h < H; ++h)
-        rv[i][h] = s_r[ks[i] + sub + 16 * h < ke[i] ? rw[i][h] - lo : 0];
+      for (int h = 0; h < H; ++h) rv[i][h] = s_r[min((unsigned)(rw[i][h] - lo), rmax)];
 #pragma unroll
     for (int i = 0; i < CPG; ++i) {
       T acc = (T)0;
