@@ -468,11 +468,11 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
   const int lo = P * PE, hi = min(m, lo + PE), len = max(0, hi - lo);
   // r's rows of the panel go straight into LDS (16-byte direct-to-LDS loads, lane l of a wave
   // at base + 16 l), all issued at once behind the first pass's panel offsets, with one wait
-  // for both (against three rounds of register staging: gradient step 48.9 -> 47.3 us).  A lane past the panel's last whole 16-byte
-  // group reads its first one (its slot lies below the panel's capacity and is never read; the
-  // last round, which would reach past the capacity, is issued only where it starts inside the
-  // panel), and the last partial group (m not a multiple of its elements) is loaded after the
-  // wait by the lane that owns it.
+  // for both (against three rounds of register staging: gradient step 48.9 -> 47.3 us).  A
+  // lane past the panel's last whole 16-byte group reads its first one (its slot lies below
+  // the panel's capacity and is never read; the last round, which would reach past the
+  // capacity, is issued only where it starts inside the panel), and the last partial group (m
+  // not a multiple of its elements) is loaded after the wait by the lane that owns it.
   constexpr int VN = 16 / (int)sizeof(T);
   const int nfull = len / VN;  // whole 16-byte groups of the panel
   auto stage_r = [&]() {
