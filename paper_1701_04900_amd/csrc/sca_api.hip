@@ -290,6 +290,16 @@ sca_status sca::alloc_workspace(sca_problem* p, const int64_t* block_ptr) {
       hipSuccess)
     return set_error(SCA_EHIP, "copy of block_ptr failed");
   p->block_ptr_host.assign(block_ptr, block_ptr + p->nblocks + 1);
+  // equal blocks (the last one possibly shorter): the in-kernel draws compute the block
+  // bounds instead of loading them
+  {
+    const int64_t B = p->nblocks > 0 ? block_ptr[1] - block_ptr[0] : 0;
+    bool uni = B > 0 && block_ptr[0] == 0;
+    for (int64_t i = 0; uni && i < p->nblocks; ++i)
+      uni = block_ptr[i] == i * B && (i + 1 < p->nblocks ? block_ptr[i + 1] == (i + 1) * B
+                                                          : block_ptr[i + 1] - block_ptr[i] <= B);
+    p->blk_uniform = uni && B <= INT32_MAX ? (int)B : 0;
+  }
   return SCA_OK;
 }
 
@@ -679,7 +689,8 @@ static void grad_fold_dense(sca_problem* p, T* x, const T* r_read, const T* base
 template <typename T>
 static void launch_round_dense(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s,
                                uint64_t Tthr, const BRParams& bp) {
-  FusedSel fs{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
+  FusedSel fs{p->d_bp,   (int)p->nblocks, 0, o->seed, Tthr, o->instance, p->blk_uniform,
+              (int)p->n};
   if (p->grad_kind == 4 && fused_draws(p)) {
     fs.on = 1;
     grad_fold_dense<T>(p, x, r, r, r, p->d_state, p->d_sel_cols, bp, fs, s);
@@ -766,7 +777,7 @@ static void launch_round_delayed(sca_problem* p, const sca_opts* o, T* x, T* r, 
                        q, (const int*)p->d_sel_cols, p->d_mbstate, p->d_mbcols);
     const T* stale_r = slot(std::max<int64_t>(0, t - stale));
     if (p->grad_kind == 4) {  // the group's S.2-S.5 fused, read from the stale version
-      const FusedSel off{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
+      const FusedSel off{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance, 0, 0};
       grad_fold_dense<T>(p, x, stale_r, slot(t), slot(t + 1), p->d_mbstate, p->d_mbcols, bp,
                          off, s);
       continue;

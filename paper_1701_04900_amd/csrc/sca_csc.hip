@@ -503,7 +503,7 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
     for (int i0 = db0; i0 < db1; i0 += 4) {
       int bv[5];
 #pragma unroll
-      for (int u = 0; u < 5; ++u) bv[u] = fs.bp[min(i0 + u, fs.nblocks)];
+      for (int u = 0; u < 5; ++u) bv[u] = fs_blk_begin(fs, min(i0 + u, fs.nblocks));
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + u;
@@ -537,7 +537,7 @@ k_dot_split(const int* __restrict__ pofs, const int* __restrict__ rowidx,
       while (dm != 0 && o < p1) {  // this thread's next drawn block that meets [p0, p1)
         const int i = db0 + __builtin_ctz(dm);
         dm &= dm - 1;
-        const int c0b = fs.bp[i], ln = fs.bp[i + 1] - c0b;
+        const int c0b = fs_blk_begin(fs, i), ln = fs_blk_len(fs, i);
         const int aa = max(o, p0), bb = min(o + ln, p1);
         oo = o;
         o += ln;
@@ -1182,7 +1182,8 @@ void grad_any(sca_problem* p, T* x, const T* r, const BRParams& bp, const FusedS
 template <typename T>
 void round_csc(sca_problem* p, const sca_opts* o, T* x, T* r, hipStream_t s, uint64_t Tthr,
                const BRParams& bp) {
-  FusedSel fs{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance};
+  FusedSel fs{p->d_bp, (int)p->nblocks, 0, o->seed, Tthr, o->instance, p->blk_uniform,
+              (int)p->n};
   fs.on = p->sp_np > 0 && p->nblocks <= kFusedSelBlocks;
   if (!fs.on) {
     prof_begin(p, s, SCA_K_SELECT);

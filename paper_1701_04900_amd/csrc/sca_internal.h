@@ -52,6 +52,7 @@ struct sca_problem {
 
   // device workspace
   int* d_bp = nullptr;
+  int blk_uniform = 0;  // > 0: every block but the last has this many columns
   double* d_cn2 = nullptr;
   sca::RoundState* d_state = nullptr;
   int* d_sel_cols = nullptr;

@@ -656,7 +656,17 @@ struct FusedSel {
   uint64_t seed;
   uint64_t T;
   uint32_t inst;
+  int bsz;    // > 0: every block but the last has bsz columns (the draw then reads no bp)
+  int ncols;  // columns (with bsz > 0)
 };
+
+// First column and length of block i.
+__device__ __forceinline__ int fs_blk_begin(const FusedSel& fs, int i) {
+  return fs.bsz > 0 ? min(i * fs.bsz, fs.ncols) : fs.bp[i];
+}
+__device__ __forceinline__ int fs_blk_len(const FusedSel& fs, int i) {
+  return fs.bsz > 0 ? min(fs.bsz, fs.ncols - i * fs.bsz) : fs.bp[i + 1] - fs.bp[i];
+}
 
 template <typename T, int Q, int C>
 struct FusedBuf {
@@ -748,7 +758,7 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
     uint32_t mask = 0;
     for (int i = b0; i < b1; ++i) {
       if (block_drawn((uint32_t)i, (uint64_t)k, fs.inst, fs.seed, fs.T)) {
-        cnt += fs.bp[i + 1] - fs.bp[i];
+        cnt += fs_blk_len(fs, i);
         mask |= 1u << (i - b0);
       }
     }
@@ -757,7 +767,7 @@ k_grad_br_fold(const T* __restrict__ A, long long lda, int m, const T* __restric
     const int u1 = (int)((long long)S * (blockIdx.x + 1) / G);
     for (int i = b0; i < b1; ++i) {
       if (mask & (1u << (i - b0))) {
-        const int c0 = fs.bp[i], len = fs.bp[i + 1] - c0;
+        const int c0 = fs_blk_begin(fs, i), len = fs_blk_len(fs, i);
         const int lo = max(off, u0), hi = min(off + len, u1);
         for (int t = lo; t < hi; ++t) s_cols[t - u0] = c0 + (t - off);
         off += len;
