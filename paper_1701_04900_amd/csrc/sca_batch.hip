@@ -539,44 +539,55 @@ k_bfused(const BInst* __restrict__ inst, const BItem* __restrict__ items,
 // r_k += the partial slots (w + k), w = the workgroups that shared instance k's items, in
 // workgroup order (instances held by one workgroup were written by it).  A workgroup whose
 // share is empty (an item costing more than a share spans several thresholds) wrote no
-// slot and is skipped.  One thread per row group; tile_base[k] = first tile (256 row
-// groups) of instance k.
+// slot and is skipped.  One thread per row group; workgroup = one tile of 256 row groups of
+// instance tile_inst[tile] (tile_base[k] = its first tile).  The slots' flags go to LDS first,
+// so that every slot is then loaded unconditionally (a skipped one is read and discarded)
+// and the loads of several slots are in flight together.
+constexpr int kBRedSlots = 1024;  // slots flagged in LDS at a time
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_bfused_reduce(int K, const BInst* __restrict__ inst, const int* __restrict__ tile_base,
-                const long long* __restrict__ item_pref, const int* __restrict__ wg_first,
-                const int* __restrict__ inst_lo, const int* __restrict__ inst_hi,
-                const BState* __restrict__ st, int G, const T* __restrict__ part, long long pst,
+k_bfused_reduce(const BInst* __restrict__ inst, const int* __restrict__ tile_base,
+                const int* __restrict__ tile_inst, const long long* __restrict__ item_pref,
+                const int* __restrict__ wg_first, const int* __restrict__ inst_lo,
+                const int* __restrict__ inst_hi, const BState* __restrict__ st, int G,
+                int ntiles, const T* __restrict__ part, long long pst,
                 T* __restrict__ r_all) {
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
-  const int ntiles = tile_base[K];
+  __shared__ unsigned char s_on[kBRedSlots];
   if (st->items == 0) return;
   const long long Tc = st->cost;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    int lo = 0, hi = K - 1;  // instance of the tile: last k with tile_base[k] <= tile
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tile_base[mid] <= tile)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const int k = lo;
+    const int k = tile_inst[tile];
     const int ilo = inst_lo[k], ihi = inst_hi[k];
     if (ilo > ihi) continue;
     const int w0 = bf_wg_of(item_pref[ilo], Tc, G), w1 = bf_wg_of(item_pref[ihi], Tc, G);
     if (w0 == w1) continue;
     const BInst& I = inst[k];
     const int nq = (I.m + VN - 1) / VN;
-    const int gi = (tile - tile_base[k]) * 256 + threadIdx.x;
-    if (gi >= nq) continue;
+    const int gi = min((tile - tile_base[k]) * 256 + (int)threadIdx.x, nq - 1);
     T* r = r_all + I.row_off + (size_t)gi * VN;
     VA s = *reinterpret_cast<const VA*>(r);
-    for (int ww = w0; ww <= w1; ++ww)
-      if (wg_first[ww] < wg_first[ww + 1])
-        s += *reinterpret_cast<const VA*>(part + (size_t)(ww + k) * pst + (size_t)gi * VN);
-    *reinterpret_cast<VA*>(r) = s;
+    for (int c0 = w0; c0 <= w1; c0 += kBRedSlots) {
+      const int c1 = min(w1 + 1, c0 + kBRedSlots);
+      __syncthreads();  // every thread is done with the previous flags
+      for (int ww = c0 + (int)threadIdx.x; ww < c1; ww += 256)
+        s_on[ww - c0] = wg_first[ww] < wg_first[ww + 1];
+      __syncthreads();
+      const T* pp = part + (size_t)(c0 + k) * pst + (size_t)gi * VN;
+      int ww = c0;
+      for (; ww + 4 <= c1; ww += 4, pp += 4 * pst) {
+        VA v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const VA*>(pp + (size_t)u * pst);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (s_on[ww + u - c0]) s += v[u];
+      }
+      for (; ww < c1; ++ww, pp += pst)
+        if (s_on[ww - c0]) s += *reinterpret_cast<const VA*>(pp);
+    }
+    if ((tile - tile_base[k]) * 256 + (int)threadIdx.x < nq) *reinterpret_cast<VA*>(r) = s;
   }
 }
 
@@ -913,7 +924,7 @@ void batch_free(sca_batch* B) {
                   B->d_tile_off, B->d_part, B->d_state, B->d_active, B->d_done, B->d_upd,
                   B->d_F, B->d_cm, B->d_cs, B->d_cz, B->d_pr, B->d_item_pref,
                   B->d_chunk_cost, B->d_wg_first, B->d_inst_lo, B->d_inst_hi,
-                  B->d_tile_base, B->d_bpart, B->d_cand};
+                  B->d_tile_base, B->d_tile_inst, B->d_bpart, B->d_cand};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (B->graph) (void)hipGraphExecDestroy(B->graph);
@@ -996,11 +1007,12 @@ void batch_round(sca_batch* B, const sca_opts* o, T* x, T* r, hipStream_t s) {
   if (fused) {
     launch_bfused<T>(B, x, r, bp, s);
     const int g = std::max(1, std::min(B->bf_tiles, 16 * B->ncu));
-    hipLaunchKernelGGL((k_bfused_reduce<T>), dim3(g), dim3(256), 0, s, B->K,
-                       (const BInst*)B->d_inst, (const int*)B->d_tile_base,
+    hipLaunchKernelGGL((k_bfused_reduce<T>), dim3(g), dim3(256), 0, s, (const BInst*)B->d_inst,
+                       (const int*)B->d_tile_base, (const int*)B->d_tile_inst,
                        (const long long*)B->d_item_pref, (const int*)B->d_wg_first,
                        (const int*)B->d_inst_lo, (const int*)B->d_inst_hi,
-                       (const BState*)B->d_state, G, (const T*)B->d_bpart, B->bf_pst, r);
+                       (const BState*)B->d_state, G, B->bf_tiles, (const T*)B->d_bpart,
+                       B->bf_pst, r);
     return;
   }
   hipLaunchKernelGGL((k_bgrad<T, 2>), dim3(2 * B->ncu), dim3(256), 0, s, (const BInst*)B->d_inst,
@@ -1233,6 +1245,12 @@ extern "C" sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t
   BALLOC(B->d_inst_lo, sizeof(int) * count);
   BALLOC(B->d_inst_hi, sizeof(int) * count);
   BALLOC(B->d_tile_base, sizeof(int) * (count + 1));
+  std::vector<int> tb(count + 1, 0);  // first fused-reduction tile (256 row groups) per instance
+  for (int64_t k = 0; k < count; ++k) {
+    const long long nq = (items[k].m + 16 / (long long)es - 1) / (16 / (long long)es);
+    tb[k + 1] = tb[k] + (int)((nq + 255) / 256);
+  }
+  BALLOC(B->d_tile_inst, sizeof(int) * std::max(1, tb[count]));
   BALLOC(B->d_cand, sizeof(int) * count);
   if (B->bf_q > 0)
     BALLOC(B->d_bpart, es * (size_t)B->bf_pst * (B->bf_gmax + count));
@@ -1250,15 +1268,14 @@ extern "C" sca_status sca_batch_create(sca_batch** out, sca_dtype dtype, int64_t
                         hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(B->d_col_inst, col_inst.data(), sizeof(int) * Ntot,
                         hipMemcpyHostToDevice) == hipSuccess;
-    std::vector<int> tb(count + 1, 0);
-    const long long VN = 16 / (long long)es;
-    for (int64_t k = 0; k < count; ++k) {
-      const long long nq = (items[k].m + VN - 1) / VN;
-      tb[k + 1] = tb[k] + (int)((nq + 255) / 256);
-    }
     B->bf_tiles = tb[count];
+    std::vector<int> ti(std::max(1, tb[count]), 0);
+    for (int64_t k = 0; k < count; ++k)
+      for (int t = tb[k]; t < tb[k + 1]; ++t) ti[t] = (int)k;
     ok = ok && hipMemcpy(B->d_tile_base, tb.data(), sizeof(int) * (count + 1),
-                         hipMemcpyHostToDevice) == hipSuccess;
+                         hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(B->d_tile_inst, ti.data(), sizeof(int) * ti.size(),
+                   hipMemcpyHostToDevice) == hipSuccess;
     // padding rows of b, r and the fold partials stay zero
     ok = ok && hipMemsetAsync(B->d_b, 0, es * Mtot, s) == hipSuccess &&
          hipMemsetAsync(B->d_rrun, 0, es * Mtot + 16, s) == hipSuccess &&

@@ -94,6 +94,7 @@ struct sca_batch {
   int* d_inst_lo = nullptr;
   int* d_inst_hi = nullptr;
   int* d_tile_base = nullptr;
+  int* d_tile_inst = nullptr;  // instance of every fused-reduction tile
   int bf_tiles = 0;
   void* d_bpart = nullptr;
   // checks of sca_batch_solve from the running residual (candidates confirmed fresh)
