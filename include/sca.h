@@ -334,11 +334,11 @@ void sca_batch_destroy(sca_batch* batch);
 sca_status sca_batch_layout(sca_batch* batch, int64_t* x_offsets_host, int64_t* r_offsets_host);
 
 /* Launch shape of the batch's rounds (Algorithm 1, steps S.1-S.5 of every instance).
- *  grad_kind 1: fused round -- one pass over the drawn columns: a 256-thread workgroup holds
+ *  grad_kind 1: fused round -- one pass over the drawn columns: a 512-thread workgroup holds
  *    a group of columns of one instance, that instance's r and its own fold partial in
- *    registers (512 threads, Q = 1, 2 or 4 row groups of 16 bytes per thread as the
- *    instance's m needs, and 4/Q columns per group: grad_cols = 4 registers of 16 bytes per
- *    thread and group); the workgroups (grad_wg_per_cu in [1, 4] per compute unit) take contiguous
+ *    registers (Q = 1, 2 or 4 row groups of 16 bytes per thread as the instance's m needs,
+ *    and 8, 4 or 1 columns per group for Q = 1, 2, 4; grad_cols = 4 names this shape and is
+ *    the only value accepted); the workgroups (grad_wg_per_cu in [1, 4] per compute unit) take contiguous
  *    shares of the round's work cut by cost (rows + 512 per drawn column), so the sums have a
  *    fixed order; a second kernel adds the partials of instances that were shared between
  *    workgroups.  Needs every instance's m <= 8192 (FP32) or <= 4096 (FP64).

@@ -337,8 +337,8 @@ k_bgrad(const BInst* __restrict__ inst, const BItem* __restrict__ items,
 // S.2-S.5 of every drawn column of every instance in one pass: a 512-thread workgroup holds
 // a group of columns of one instance in registers -- thread t owns the 16-byte row groups
 // t, t + 512, ..., t + (Q-1)*512 of each, Q = the instance's row groups per thread (1, 2 or
-// 4), C = 4/Q columns per group, so a group is 64 bytes per thread whatever m -- with
-// the same rows of the instance's r and of its own fold partial.  Workgroup w takes a
+// 4), C = bf_cols(Q) columns per group (128 bytes per thread for Q <= 2, 64 for Q = 4) --
+// with the same rows of the instance's r and of its own fold partial.  Workgroup w takes a
 // contiguous share of the round's items (the shares are cut by cost, rows plus a fixed part
 // per column, see k_bsel_scatter), so every partial sum has a fixed order.  When its share
 // moves on to the next instance, the workgroup writes its partial: straight into r when it
@@ -351,7 +351,15 @@ constexpr int kBFThreads = 512;
 constexpr int kBFWaves = kBFThreads / 64;
 constexpr int kBFMaxQ = 4;        // FP32 m <= 8192, FP64 m <= 4096
 constexpr int kBFMaxWgPerCu = 4;  // the partial slots are allocated for this many
-constexpr int kBFSlots = 4;       // 16-byte registers per thread and group (C * Q)
+constexpr int kBFSlots = 4;       // the grad_cols value of this kernel's launch shape
+// Columns per group for Q row groups of 16 bytes per thread: 8 (Q = 1), 4 (Q = 2), 1 (Q = 4),
+// so that a group is 128 bytes per thread where Q <= 2 (64 bytes for Q = 4: a larger group
+// there exceeds the 128 registers of two workgroups per CU).  Against 4/Q columns (64 bytes
+// for every Q), the batched solve of 256 instances with m in [500, 8000]: 15.1 -> 14.0 s
+// (6 registers of the FP32 kernel spill; 6 columns for Q = 1: 16.5 s; 2 columns for Q = 4:
+// 14.4 s).
+constexpr int bf_cols(int Q) { return Q == 1 ? 8 : Q == 2 ? 4 : 1; }
+constexpr int kBFMaxC = bf_cols(1);
 
 __device__ __forceinline__ int bf_wg_of(long long pref, long long Tc, int G) {
   return (int)min((long long)(G - 1), pref * G / Tc);
@@ -362,7 +370,7 @@ __device__ __forceinline__ int bf_q_of(int nq) {
   return nq <= kBFThreads ? 1 : nq <= 2 * kBFThreads ? 2 : 4;
 }
 
-// One group of C = kBFSlots / Q consecutive columns j0 .. j0+cnt-1 of instance I: the
+// One group of C = bf_cols(Q) consecutive columns j0 .. j0+cnt-1 of instance I: the
 // columns' row groups (masked past m), the C dot products with r (wave sums, then the 8
 // wave sums in a fixed order), the best responses and moves (threads c < cnt, broadcast
 // through LDS) and the fold into this thread's rows of the partial.
@@ -377,7 +385,7 @@ __device__ __forceinline__ void bf_group(const BInst& I, int nq, int j0, int cnt
                                          const double* __restrict__ cn2, long long& moved) {
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
-  constexpr int C = kBFSlots / Q;
+  constexpr int C = bf_cols(Q);
   const char* A = reinterpret_cast<const char*>(I.A);
   // the best-response inputs of column tid (threads < cnt) are loaded with the column
   T xj = (T)0;
@@ -450,8 +458,8 @@ k_bfused(const BInst* __restrict__ inst, const BItem* __restrict__ items,
          long long pst, BRParams bp0) {
   typedef typename V16<T>::v VA;
   constexpr int VN = V16<T>::N;
-  __shared__ T red[kBFSlots][kBFWaves];
-  __shared__ T s_d[kBFSlots];
+  __shared__ T red[kBFMaxC][kBFWaves];
+  __shared__ T s_d[kBFMaxC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = gridDim.x, w = blockIdx.x;
   if (st->items == 0) return;
@@ -511,7 +519,7 @@ k_bfused(const BInst* __restrict__ inst, const BItem* __restrict__ items,
     bp.c2 = 2.0 * I.c;
     bp.beta = I.beta;
     const int j00 = sel_cols[it.pos];
-    const int C = kBFSlots / qk;
+    const int C = bf_cols(qk);
     for (int cs = 0; cs < it.cnt; cs += C) {
       const int cnt = min(C, it.cnt - cs);
       switch (qk) {
@@ -1363,8 +1371,8 @@ extern "C" sca_status sca_batch_set_launch(sca_batch* B, const sca_launch* l) {
       return set_error(SCA_EINVAL, "the fused round needs every m <= %d (this dtype)",
                        kBFThreads * kBFMaxQ * (int)(16 / B->esize));
     if (l->grad_cols != kBFSlots)
-      return set_error(SCA_EINVAL, "fused batch round: grad_cols must be %d (16-byte registers "
-                       "per thread and group: columns x row groups)", kBFSlots);
+      return set_error(SCA_EINVAL, "fused batch round: grad_cols must be %d (the kernel groups "
+                       "8, 4 or 1 columns by the instance's m)", kBFSlots);
     if (l->grad_wg_per_cu < 1 || l->grad_wg_per_cu > kBFMaxWgPerCu)
       return set_error(SCA_EINVAL, "fused batch round: grad_wg_per_cu must lie in [1, %d]",
                        kBFMaxWgPerCu);
