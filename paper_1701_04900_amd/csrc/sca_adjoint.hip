@@ -409,6 +409,11 @@ sca_status adj_alloc(AdjWork* W, int K, long long Ntot, long long Mtot) {
 }
 
 // The whole adjoint for K instances.  r64 must hold A x* - b (FP64) in the r layout.
+// Zeroes count ints (a fill kernel rather than a memset node, for callers that capture).
+__global__ void __launch_bounds__(256) k_adj_zero_int(int* __restrict__ a, int count) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) a[i] = 0;
+}
+
 template <typename T>
 sca_status adjoint_core(AdjWork* W, int dtype, int ncu, const BInst* d_inst,
                         const std::vector<BInst>& hinst, const double* d_cn2, const double* r64,
@@ -479,7 +484,7 @@ sca_status adjoint_core(AdjWork* W, int dtype, int ncu, const BInst* d_inst,
   // CG start: w = 0, res = p = xbar_S
   hipLaunchKernelGGL(k_adj_init, dim3(eg), dim3(256), 0, s, W->Ntot, (const int*)W->S_idx,
                      (const AState*)W->st, (const void*)xbar, dtype, W->w, W->res, W->p);
-  (void)hipMemsetAsync(W->iters, 0, sizeof(int) * K, s);
+  hipLaunchKernelGGL(k_adj_zero_int, dim3(kg), dim3(256), 0, s, W->iters, K);
   hipLaunchKernelGGL(k_adj_segdot, dim3(std::min(K, 4 * ncu)), dim3(256), 0, s, K,
                      (const int*)W->S_lo, (const int*)W->S_n, (const double*)W->res,
                      (const double*)W->res, W->sc, (int)SC_RR, (const int*)nullptr);
