@@ -339,7 +339,7 @@ sca_status sca_batch_layout(sca_batch* batch, int64_t* x_offsets_host, int64_t* 
  *    registers (Q = 1, 2 or 4 row groups of 16 bytes per thread as the instance's m needs,
  *    and 8, 4 or 1 columns per group for Q = 1, 2, 4; grad_cols = 4 names this shape and is
  *    the only value accepted); the workgroups (grad_wg_per_cu in [1, 4] per compute unit) take contiguous
- *    shares of the round's work cut by cost (rows + 512 per drawn column), so the sums have a
+ *    shares of the round's work cut by cost (rows + 16384 per drawn column), so the sums have a
  *    fixed order; a second kernel adds the partials of instances that were shared between
  *    workgroups.  Needs every instance's m <= 8192 (FP32) or <= 4096 (FP64).
  *  grad_kind 0: two-pass round (gradient pass, then an ordered fold of the moved columns).
